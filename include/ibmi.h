@@ -1,0 +1,164 @@
+/*
+ * ibmi.h -- C ABI of the MI355X (gfx950) IBMI library, libibmi.so.
+ *
+ * IBMI (Iterative Block Matrix Inversion; Paterson, Pestana and Dolean) refines an
+ * approximation H of A^{-1} for a dense symmetric positive definite A.  The problem as the
+ * paper states it (Algorithm 1): given A, a tolerance, index sets I_1..I_K and an initial
+ * approximation of the inverse Schur complement on I_1^c, return the final H and the
+ * number of iterations r.  Every iteration ("sweep") applies the approximate block
+ * inverse of eq. (IBMI) for k = 1..K in order, always using the latest H:
+ *
+ *     W = A_I^{-1} A_{I,I^c}
+ *     H[I,I^c] = -W H[I^c,I^c]        H[I^c,I] = H[I,I^c]^T
+ *     H[I,I]   = A_I^{-1} + W H[I^c,I^c] W^T
+ *
+ * and H[I^c,I^c] is left unchanged.  This library checks ||I - A H||_F after each sweep.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense, row-major, FP64, with a leading dimension (elements between rows).
+ *    A is symmetric, so for A the layout is immaterial.  H is written in full (both
+ *    triangles) and is bitwise symmetric after every sweep.
+ *  - Pointers named d* are device pointers (HIP device memory of the current device);
+ *    all others are host pointers.
+ *  - The caller owns A, H and the workspace.  The library never allocates device memory:
+ *    all scratch lives in the caller's workspace, sized by ibmi_workspace_bytes().
+ *  - All device work is enqueued on the plan's HIP stream.  A plan is not thread-safe;
+ *    distinct plans on distinct streams may run concurrently.
+ *  - Every function returns an ibmi_status; nothing else crosses the ABI.
+ */
+#ifndef IBMI_H_
+#define IBMI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IBMI_OK = 0,
+  IBMI_ERR_INVALID_ARG = 1,   /* bad size, pointer, partition, option                     */
+  IBMI_ERR_NOT_SPD = 2,       /* a diagonal block A_{I_k} has a non-positive/NaN pivot   */
+  IBMI_ERR_OUT_OF_MEMORY = 3, /* the workspace given is smaller than required            */
+  IBMI_ERR_HIP = 4,           /* a HIP runtime call failed                               */
+  IBMI_ERR_NONFINITE = 5      /* the residual became NaN or Inf                          */
+} ibmi_status;
+
+/* Arithmetic of the H-update products.  FP64 everywhere is the paper's method.  The
+ * FP32 form runs the update products in FP32 on the matrix cores (FP32 accumulation) in
+ * the correction form driven by an FP64 residual; block factors and the residual stay FP64. */
+typedef enum { IBMI_PREC_FP64 = 0, IBMI_PREC_FP32_UPDATE = 1 } ibmi_precision;
+
+/* Initial approximation (Algorithm 1 input; only H0[I_1^c, I_1^c] is read).
+ * IDENTITY is the paper's default choice.  BLOCKDIAG_INV sets H0 = blockdiag(A_{I_k}^{-1})
+ * and needs disjoint sets.  GIVEN uses the caller's H as passed to ibmi_solve (resume). */
+typedef enum { IBMI_INIT_IDENTITY = 0, IBMI_INIT_BLOCKDIAG_INV = 1, IBMI_INIT_GIVEN = 2 } ibmi_init;
+
+/* Stop test after each sweep.  FRO: ||I - A H||_F < tol.  REL_BOUND:
+ * ||I - A H||_F / (lambda_min * ||H||_F) < tol, a bound on the relative Frobenius error of
+ * H when lambda_min is a lower bound on the smallest eigenvalue of A (e.g. the nugget of a
+ * covariance matrix). */
+typedef enum { IBMI_STOP_FRO = 0, IBMI_STOP_REL_BOUND = 1 } ibmi_stop;
+
+typedef struct {
+  int64_t p;               /* order of A                                                  */
+  int32_t block_rows;      /* partitioner: rows per interior set (max 1024)                */
+  int32_t overlap;         /* partitioner: rows shared by consecutive sets (< block_rows)  */
+  const int64_t* bounds;   /* optional host array of n_blocks [start, end) pairs; NULL =   */
+  int32_t n_blocks;        /*   use the partitioner.  Sets must cover [0,p), sorted by start */
+  int32_t precision;       /* ibmi_precision                                               */
+  int32_t init;            /* ibmi_init                                                    */
+  int32_t stop;            /* ibmi_stop                                                    */
+  double tol;              /* > 0                                                          */
+  double lambda_min;       /* > 0 when stop = REL_BOUND                                    */
+  int32_t max_sweeps;      /* >= 1; hitting it is not an error (converged = 0)             */
+  int32_t stagnation_guard;/* 1: stop (floor_limited = 1) when the residual fell < 1% in   */
+                           /*    each of the last 3 sweeps while already below 100 tol     */
+  int32_t fixed_sweeps;    /* > 0: run exactly this many sweeps, ignore tol and the guard  */
+  int32_t reserved;
+} ibmi_options;
+
+typedef struct {
+  int32_t sweeps;          /* sweeps completed (r in Algorithm 1)                          */
+  int32_t converged;       /* 1 if the stop test passed                                    */
+  int32_t failed_block;    /* set index k with a bad pivot (NOT_SPD), else -1              */
+  int32_t floor_limited;   /* 1 if the stagnation guard stopped the loop                   */
+  double residual;         /* ||I - A H||_F after the last sweep                           */
+  double stop_value;       /* the quantity compared with tol                               */
+} ibmi_info;
+
+typedef struct ibmi_plan_s* ibmi_plan_t;
+
+/* Human-readable name of a status code (static string). */
+const char* ibmi_status_str(ibmi_status s);
+
+/* The default partition (host only, no device work): the multi-block overlapping sets of
+ * the paper's multi-block section with end sets of m+h rows and interior sets of m+2h rows
+ * (cost section).  Core stride m = block_rows - overlap, K = ceil(p/m) (K = 1 if
+ * p <= block_rows), each core extended by floor(overlap/2) rows left and ceil(overlap/2)
+ * rows right, clipped to [0,p); a last core shorter than overlap merges into the previous.
+ * Writes up to `capacity` pairs to bounds_out (may be NULL to query) and the count to
+ * *n_out.  INVALID_ARG if p < 1, block_rows < 1, overlap < 0 or overlap >= block_rows. */
+ibmi_status ibmi_partition(int64_t p, int32_t block_rows, int32_t overlap,
+                           int64_t* bounds_out, int32_t capacity, int32_t* n_out);
+
+/* Device workspace (bytes) a plan with these options needs; 0 if the options are invalid.
+ * Used for admission by HBM footprint. */
+size_t ibmi_workspace_bytes(const ibmi_options* opts);
+
+/* Build a plan: partition, then for every set (all sets in one launch each) the Cholesky
+ * factor of A_{I_k}, A_{I_k}^{-1} (symmetrised) and W_k = A_{I_k}^{-1} A_{I_k,I_k^c}.  These
+ * depend on A only, so they are computed once and reused by every sweep.
+ *  dA       p x p SPD matrix, leading dimension lda >= p.  Borrowed: must stay alive and
+ *           unmodified until ibmi_plan_destroy.  Must not overlap H or the workspace.
+ *  dWork    device workspace of at least ibmi_workspace_bytes(opts) bytes, 256-byte
+ *           aligned.  Borrowed like dA.
+ *  stream   hipStream_t to enqueue on (NULL = default stream).
+ * Synchronises the stream once to read the pivot status.  On NOT_SPD no plan is returned
+ * and ibmi_plan_failed_block() reports the set.  *out is set only on IBMI_OK. */
+ibmi_status ibmi_plan(ibmi_plan_t* out, const ibmi_options* opts, const double* dA, int64_t lda,
+                      void* dWork, size_t work_bytes, void* stream);
+
+/* Set index of the last NOT_SPD failure of ibmi_plan on this thread (-1 if none). */
+int32_t ibmi_plan_failed_block(void);
+
+/* Number of sets and their [start, end) bounds (host array of 2*n, may be NULL). */
+ibmi_status ibmi_plan_blocks(ibmi_plan_t plan, int32_t* n_blocks, int64_t* bounds);
+
+/* Run Algorithm 1: initialise H per opts->init, then sweeps until the stop test passes,
+ * max_sweeps is reached or the guard fires.  dH is p x p with leading dimension ldh >= p,
+ * written in place (read as well for INIT_GIVEN).  Synchronises once per sweep to read the
+ * residual.  info (host, required) receives the outcome; history (host, nullable, length
+ * max_sweeps or fixed_sweeps) receives ||I - A H||_F after each sweep.
+ * NONFINITE if the residual is NaN/Inf (H then holds the offending iterate). */
+ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* info, double* history);
+
+/* Enqueue one application of eq. (IBMI) for set k (0-based) on dH, with no
+ * synchronisation.  Reads H[I_k^c, I_k^c], writes rows and columns I_k. */
+ibmi_status ibmi_block_step(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t k);
+
+/* Enqueue the initial H of opts->init (IDENTITY or BLOCKDIAG_INV; GIVEN leaves dH as is). */
+ibmi_status ibmi_init_h(ibmi_plan_t plan, double* dH, int64_t ldh);
+
+/* ||I - A H||_F for the plan's A (FP64, deterministic fixed-order reduction).  Synchronises
+ * the plan's stream and writes the value to *out (host). */
+ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, double* out);
+
+/* Kernel timing, for measurement.  While enabled, each panel GEMM (V = W H[I^c,I^c] with its
+ * scatter into H), each diagonal update (split-K W H[I^c,I] plus the finalisation of H[I,I])
+ * and each residual launch is bracketed by HIP events on the plan's stream.
+ * ibmi_kernel_times synchronises the stream, then returns and resets, per category
+ * (0 = panel, 1 = diagonal, 2 = residual): accumulated milliseconds, launch counts and the
+ * algorithmic flops of those launches (2 b c^2, 2 b^2 c and 2 p^3 respectively).  Arrays are
+ * host arrays of length 3; any may be NULL. */
+ibmi_status ibmi_set_profiling(ibmi_plan_t plan, int32_t on);
+ibmi_status ibmi_kernel_times(ibmi_plan_t plan, double* ms, int64_t* launches, double* flops);
+
+/* Release the host-side plan object.  Does not free A or the workspace (caller-owned). */
+ibmi_status ibmi_plan_destroy(ibmi_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBMI_H_ */

@@ -24,14 +24,15 @@ unpinned" except where a docstring says so.
 """
 from .partition import partition, validate_blocks, complement
 from .ibmi import (
-    IbmiError, plan, initial_h, block_update, sweep, residual_fro, paper_error,
+    IbmiError, plan, block_factors, initial_h, block_update, sweep, residual_fro, paper_error,
     ibmi_solve, flops_plan, flops_sweep, correction_sweep, emulate_product,
 )
 from .cholinv import cholesky_inverse_loops
 from .exact import exact_ibmi, exact_residual_sq
 
 __all__ = [
-    "partition", "validate_blocks", "complement", "IbmiError", "plan", "initial_h",
+    "partition", "validate_blocks", "complement", "IbmiError", "plan", "block_factors",
+    "initial_h",
     "block_update", "sweep", "residual_fro", "paper_error", "ibmi_solve", "flops_plan",
     "flops_sweep", "correction_sweep", "emulate_product", "cholesky_inverse_loops",
     "exact_ibmi", "exact_residual_sq",

@@ -78,23 +78,30 @@ def plan(a: np.ndarray, blocks) -> list:
     if not np.array_equal(a, a.T):
         raise IbmiError("INVALID_ARG", "A must be exactly symmetric")
     p = a.shape[0]
-    out = []
-    for k, idx in enumerate(_index_sets(p, blocks)):
-        comp = complement(p, idx)
-        a_i = a[np.ix_(idx, idx)]
-        try:
-            chol = np.linalg.cholesky(a_i)
-        except np.linalg.LinAlgError:
-            raise IbmiError("NOT_SPD", f"diagonal block {k} is not positive definite", k) from None
-        d = np.diag(chol)
-        if not (np.isfinite(d).all() and (d > 0).all()):
-            raise IbmiError("NOT_SPD", f"diagonal block {k} has a bad pivot", k)
-        linv = solve_triangular(chol, np.eye(idx.size), lower=True)
-        ainv = linv.T @ linv
-        ainv = 0.5 * (ainv + ainv.T)
-        w = ainv @ a[np.ix_(idx, comp)]
-        out.append(BlockPlan(idx, comp, chol, ainv, w))
-    return out
+    return [plan_one(a, idx, k) for k, idx in enumerate(_index_sets(p, blocks))]
+
+
+def block_factors(a: np.ndarray, s: int, e: int) -> BlockPlan:
+    """The factors of one contiguous set [s, e) alone (same steps as ``plan``), for checking
+    single block steps on matrices too large for a full CPU sweep."""
+    return plan_one(np.asarray(a, dtype=np.float64), np.arange(s, e), 0)
+
+
+def plan_one(a: np.ndarray, idx: np.ndarray, k: int) -> BlockPlan:
+    comp = complement(a.shape[0], idx)
+    a_i = a[np.ix_(idx, idx)]
+    try:
+        chol = np.linalg.cholesky(a_i)
+    except np.linalg.LinAlgError:
+        raise IbmiError("NOT_SPD", f"diagonal block {k} is not positive definite", k) from None
+    d = np.diag(chol)
+    if not (np.isfinite(d).all() and (d > 0).all()):
+        raise IbmiError("NOT_SPD", f"diagonal block {k} has a bad pivot", k)
+    linv = solve_triangular(chol, np.eye(idx.size), lower=True)
+    ainv = linv.T @ linv
+    ainv = 0.5 * (ainv + ainv.T)
+    w = ainv @ a[np.ix_(idx, comp)]
+    return BlockPlan(idx, comp, chol, ainv, w)
 
 
 def initial_h(a: np.ndarray, blocks_plan: list, kind: str = "identity", h0=None) -> np.ndarray:

@@ -1,0 +1,574 @@
+// Host side of libibmi: partitioner, plan (block factors), sweep driver and the C ABI
+// declared in include/ibmi.h.  All device work goes through the kernels in kernels.hip.
+#include "ibmi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+
+using ibmi::BlockDesc;
+using ibmi::GemmCfg;
+using ibmi::IdxMap;
+using ibmi::Opnd;
+
+namespace {
+
+constexpr int64_t kMaxBlockRows = 1024;  // LDS panel and register-slot limits of the factor kernels
+constexpr size_t kAlign = 256;
+
+thread_local int32_t g_last_failed_block = -1;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+#define IBMI_HIP(call)                          \
+  do {                                          \
+    if ((call) != hipSuccess) return IBMI_ERR_HIP; \
+  } while (0)
+
+// The partition reading documented in ibmi.h (ibmi_partition).
+void default_partition(int64_t p, int64_t b, int64_t ovl, std::vector<int64_t>& s,
+                       std::vector<int64_t>& e) {
+  s.clear();
+  e.clear();
+  if (p <= b) {
+    s.push_back(0);
+    e.push_back(p);
+    return;
+  }
+  const int64_t m = b - ovl;
+  int64_t k_sets = (p + m - 1) / m;
+  std::vector<int64_t> cs, ce;
+  for (int64_t k = 0; k < k_sets; ++k) {
+    cs.push_back(k * m);
+    ce.push_back(std::min((k + 1) * m, p));
+  }
+  if (k_sets > 1 && ce.back() - cs.back() < ovl) {
+    ce[k_sets - 2] = ce.back();
+    cs.pop_back();
+    ce.pop_back();
+    --k_sets;
+  }
+  const int64_t hl = ovl / 2, hr = ovl - ovl / 2;
+  for (int64_t k = 0; k < k_sets; ++k) {
+    s.push_back(std::max<int64_t>(0, cs[k] - hl));
+    e.push_back(std::min(p, ce[k] + hr));
+  }
+}
+
+// Validated sets of a plan (partitioner or explicit bounds).
+ibmi_status make_sets(const ibmi_options* o, std::vector<int64_t>& s, std::vector<int64_t>& e) {
+  if (!o || o->p < 1) return IBMI_ERR_INVALID_ARG;
+  const int64_t p = o->p;
+  if (o->bounds) {
+    if (o->n_blocks < 1) return IBMI_ERR_INVALID_ARG;
+    s.assign(o->n_blocks, 0);
+    e.assign(o->n_blocks, 0);
+    for (int k = 0; k < o->n_blocks; ++k) {
+      s[k] = o->bounds[2 * k];
+      e[k] = o->bounds[2 * k + 1];
+    }
+  } else {
+    if (o->block_rows < 1 || o->overlap < 0 || o->overlap >= o->block_rows)
+      return IBMI_ERR_INVALID_ARG;
+    default_partition(p, o->block_rows, o->overlap, s, e);
+  }
+  // sorted by start, non-empty, inside [0,p), covering, each within the size limit
+  int64_t covered_to = 0;
+  for (size_t k = 0; k < s.size(); ++k) {
+    if (s[k] < 0 || e[k] > p || s[k] >= e[k]) return IBMI_ERR_INVALID_ARG;
+    if (k > 0 && s[k] < s[k - 1]) return IBMI_ERR_INVALID_ARG;
+    if (e[k] - s[k] > kMaxBlockRows) return IBMI_ERR_INVALID_ARG;
+    if (s[k] > covered_to) return IBMI_ERR_INVALID_ARG;
+    covered_to = std::max(covered_to, e[k]);
+  }
+  if (covered_to != p) return IBMI_ERR_INVALID_ARG;
+  if (o->init == IBMI_INIT_BLOCKDIAG_INV) {
+    for (size_t k = 1; k < s.size(); ++k)
+      if (s[k] < e[k - 1]) return IBMI_ERR_INVALID_ARG;
+  }
+  return IBMI_OK;
+}
+
+ibmi_status check_options(const ibmi_options* o) {
+  if (!o) return IBMI_ERR_INVALID_ARG;
+  if (!(o->tol > 0.0) || o->max_sweeps < 1 || o->fixed_sweeps < 0) return IBMI_ERR_INVALID_ARG;
+  if (o->precision != IBMI_PREC_FP64) return IBMI_ERR_INVALID_ARG;
+  if (o->init < IBMI_INIT_IDENTITY || o->init > IBMI_INIT_GIVEN) return IBMI_ERR_INVALID_ARG;
+  if (o->stop != IBMI_STOP_FRO && o->stop != IBMI_STOP_REL_BOUND) return IBMI_ERR_INVALID_ARG;
+  if (o->stop == IBMI_STOP_REL_BOUND && !(o->lambda_min > 0.0)) return IBMI_ERR_INVALID_ARG;
+  return IBMI_OK;
+}
+
+GemmCfg env_cfg(const char* name, GemmCfg dflt) {
+  const char* v = std::getenv(name);
+  if (!v) return dflt;
+  const int i = std::atoi(v);
+  return (i >= 0 && i < ibmi::GEMM_CFG_COUNT) ? (GemmCfg)i : dflt;
+}
+
+struct Tuning {
+  GemmCfg panel = ibmi::GEMM_64x64, diag = ibmi::GEMM_64x64, resid = ibmi::GEMM_64x64,
+          plan = ibmi::GEMM_64x64;
+  int diag_splits = 0;  // 0 = automatic
+};
+
+Tuning tuning_for(int64_t /*p*/) {
+  Tuning t;
+  t.panel = env_cfg("IBMI_CFG_PANEL", t.panel);
+  t.diag = env_cfg("IBMI_CFG_DIAG", t.diag);
+  t.resid = env_cfg("IBMI_CFG_RESID", t.resid);
+  t.plan = env_cfg("IBMI_CFG_PLAN", t.plan);
+  if (const char* v = std::getenv("IBMI_DIAG_SPLITS")) t.diag_splits = std::max(1, std::atoi(v));
+  return t;
+}
+
+int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
+  if (c <= 0) return 1;
+  if (forced > 0) return (int)std::min<int64_t>(forced, std::max<int64_t>(1, c / 64));
+  const int64_t tiles = ibmi::gemm_resid_slots(cfg, b, b);
+  int64_t want = (512 + tiles - 1) / tiles;
+  want = std::min<int64_t>(want, std::max<int64_t>(1, c / 512));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, 32));
+}
+
+// Workspace layout (offsets in bytes from the workspace base).
+struct Layout {
+  size_t desc = 0, fac = 0, wt = 0, part = 0, red = 0, red2 = 0, scal = 0, status = 0, total = 0;
+  std::vector<BlockDesc> blocks;
+  std::vector<int64_t> wt_off;  // doubles, relative to wt
+  int64_t b_max = 0;
+  int splits = 1;
+  int64_t red_len = 0;
+};
+
+Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
+                   const std::vector<int64_t>& e, const Tuning& t) {
+  Layout L;
+  const int64_t p = o->p;
+  const int K = (int)s.size();
+  int64_t fac = 0, wt = 0;
+  for (int k = 0; k < K; ++k) {
+    const int64_t b = e[k] - s[k], c = p - b;
+    BlockDesc d;
+    d.s = s[k];
+    d.b = b;
+    d.l_off = fac;
+    d.linv_off = fac + b * b;
+    d.ainv_off = fac + 2 * b * b;
+    fac += 3 * b * b;
+    L.blocks.push_back(d);
+    L.wt_off.push_back(wt);
+    wt += c * b;
+    L.b_max = std::max(L.b_max, b);
+    L.splits = std::max(L.splits, diag_splits_for(b, c, t.diag, t.diag_splits));
+  }
+  L.red_len = std::max<int64_t>(ibmi::gemm_resid_slots(t.resid, p, p), 1);
+  size_t off = 0;
+  L.desc = off;
+  off = align_up(off + K * sizeof(BlockDesc));
+  L.fac = off;
+  off = align_up(off + (size_t)fac * 8);
+  L.wt = off;
+  off = align_up(off + (size_t)wt * 8);
+  L.part = off;
+  off = align_up(off + (size_t)L.splits * L.b_max * L.b_max * 8);
+  L.red = off;
+  off = align_up(off + (size_t)L.red_len * 8);
+  L.red2 = off;
+  off = align_up(off + (size_t)1024 * 8);
+  L.scal = off;
+  off = align_up(off + 8 * 8);
+  L.status = off;
+  off = align_up(off + 4 * sizeof(int));
+  L.total = off;
+  return L;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+// HIP event pairs bracketing launches of one category, collected after a stream sync.
+struct Timer {
+  std::vector<hipEvent_t> free_ev;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0.0, flops = 0.0;
+  int64_t launches = 0;
+  hipEvent_t get() {
+    if (!free_ev.empty()) {
+      hipEvent_t e = free_ev.back();
+      free_ev.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void collect() {
+    for (auto& pr : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(pr.second) == hipSuccess &&
+          hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess)
+        ms += t;
+      free_ev.push_back(pr.first);
+      free_ev.push_back(pr.second);
+    }
+    pending.clear();
+  }
+  ~Timer() {
+    collect();
+    for (hipEvent_t e : free_ev) (void)hipEventDestroy(e);
+  }
+};
+
+struct ibmi_plan_s {
+  ibmi_options o;
+  bool profiling = false;
+  Timer timers[3];
+  std::vector<int64_t> s, e;
+  int64_t p = 0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  hipStream_t st = nullptr;
+  char* work = nullptr;
+  size_t work_bytes = 0;
+  Layout L;
+  Tuning t;
+  double* fac() const { return (double*)(work + L.fac); }
+  double* wt(int k) const { return (double*)(work + L.wt) + L.wt_off[k]; }
+  double* ainv(int k) const { return fac() + L.blocks[k].ainv_off; }
+  double* part() const { return (double*)(work + L.part); }
+  double* red() const { return (double*)(work + L.red); }
+  double* red2() const { return (double*)(work + L.red2); }
+  double* scal() const { return (double*)(work + L.scal); }
+  int* status() const { return (int*)(work + L.status); }
+  BlockDesc* desc() const { return (BlockDesc*)(work + L.desc); }
+};
+
+extern "C" {
+
+const char* ibmi_status_str(ibmi_status s) {
+  switch (s) {
+    case IBMI_OK: return "IBMI_OK";
+    case IBMI_ERR_INVALID_ARG: return "IBMI_ERR_INVALID_ARG";
+    case IBMI_ERR_NOT_SPD: return "IBMI_ERR_NOT_SPD";
+    case IBMI_ERR_OUT_OF_MEMORY: return "IBMI_ERR_OUT_OF_MEMORY";
+    case IBMI_ERR_HIP: return "IBMI_ERR_HIP";
+    case IBMI_ERR_NONFINITE: return "IBMI_ERR_NONFINITE";
+  }
+  return "IBMI_UNKNOWN_STATUS";
+}
+
+ibmi_status ibmi_partition(int64_t p, int32_t block_rows, int32_t overlap, int64_t* bounds_out,
+                           int32_t capacity, int32_t* n_out) {
+  if (p < 1 || block_rows < 1 || overlap < 0 || overlap >= block_rows || !n_out)
+    return IBMI_ERR_INVALID_ARG;
+  std::vector<int64_t> s, e;
+  default_partition(p, block_rows, overlap, s, e);
+  *n_out = (int32_t)s.size();
+  if (bounds_out) {
+    const int n = std::min<int>(capacity, (int)s.size());
+    for (int k = 0; k < n; ++k) {
+      bounds_out[2 * k] = s[k];
+      bounds_out[2 * k + 1] = e[k];
+    }
+  }
+  return IBMI_OK;
+}
+
+size_t ibmi_workspace_bytes(const ibmi_options* opts) {
+  if (check_options(opts) != IBMI_OK) return 0;
+  std::vector<int64_t> s, e;
+  if (make_sets(opts, s, e) != IBMI_OK) return 0;
+  return make_layout(opts, s, e, tuning_for(opts->p)).total;
+}
+
+int32_t ibmi_plan_failed_block(void) { return g_last_failed_block; }
+
+ibmi_status ibmi_plan(ibmi_plan_t* out, const ibmi_options* opts, const double* dA, int64_t lda,
+                      void* dWork, size_t work_bytes, void* stream) {
+  g_last_failed_block = -1;
+  if (!out || !dA || !dWork) return IBMI_ERR_INVALID_ARG;
+  ibmi_status rc = check_options(opts);
+  if (rc != IBMI_OK) return rc;
+  if (lda < opts->p || ((uintptr_t)dWork % kAlign) != 0) return IBMI_ERR_INVALID_ARG;
+  auto* P = new ibmi_plan_s();
+  P->o = *opts;
+  P->o.bounds = nullptr;  // the plan keeps its own copy of the sets
+  P->p = opts->p;
+  P->A = dA;
+  P->lda = lda;
+  P->st = (hipStream_t)stream;
+  P->t = tuning_for(P->p);
+  rc = make_sets(opts, P->s, P->e);
+  if (rc != IBMI_OK) {
+    delete P;
+    return rc;
+  }
+  P->L = make_layout(opts, P->s, P->e, P->t);
+  if (work_bytes < P->L.total) {
+    delete P;
+    return IBMI_ERR_OUT_OF_MEMORY;
+  }
+  const size_t a_bytes = (size_t)((P->p - 1) * lda + P->p) * 8;
+  if (ranges_overlap(dA, a_bytes, dWork, P->L.total)) {
+    delete P;
+    return IBMI_ERR_INVALID_ARG;
+  }
+  P->work = (char*)dWork;
+  P->work_bytes = work_bytes;
+  const int K = (int)P->s.size();
+  hipStream_t st = P->st;
+  auto fail = [&](ibmi_status r) {
+    delete P;
+    return r;
+  };
+  if (hipMemcpyAsync(P->desc(), P->L.blocks.data(), K * sizeof(BlockDesc), hipMemcpyHostToDevice,
+                     st) != hipSuccess)
+    return fail(IBMI_ERR_HIP);
+  if (ibmi::fill_int(P->status(), INT_MAX, 1, st) != hipSuccess) return fail(IBMI_ERR_HIP);
+  if (ibmi::chol_factor(P->desc(), K, P->L.b_max, P->A, P->lda, P->fac(), P->status(), st) !=
+      hipSuccess)
+    return fail(IBMI_ERR_HIP);
+  int status = INT_MAX;
+  if (hipMemcpyAsync(&status, P->status(), sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(IBMI_ERR_HIP);
+  if (status != INT_MAX) {
+    g_last_failed_block = status;
+    return fail(IBMI_ERR_NOT_SPD);
+  }
+  if (ibmi::chol_linv(P->desc(), K, P->L.b_max, P->fac(), st) != hipSuccess)
+    return fail(IBMI_ERR_HIP);
+  for (int k = 0; k < K; ++k) {
+    const BlockDesc& d = P->L.blocks[k];
+    const int64_t b = d.b, c = P->p - b;
+    double* linv = P->fac() + d.linv_off;
+    double* tmp = P->fac() + d.l_off;  // the factor L is no longer needed
+    Opnd Xl{linv, b, IdxMap{}, IdxMap{}};
+    if (ibmi::gemm_store(P->t.plan, Xl, Xl, b, b, b, tmp, b, st) != hipSuccess)
+      return fail(IBMI_ERR_HIP);
+    if (ibmi::symmetrize_block(tmp, P->ainv(k), b, st) != hipSuccess) return fail(IBMI_ERR_HIP);
+    if (c > 0) {
+      const IdxMap g{0, d.s, b};
+      Opnd Xa{P->A, P->lda, IdxMap{d.s, INT64_MAX, 0}, g};
+      Opnd Yi{P->ainv(k), b, IdxMap{}, IdxMap{}};
+      if (ibmi::gemm_store(P->t.plan, Xa, Yi, c, b, b, P->wt(k), b, st) != hipSuccess)
+        return fail(IBMI_ERR_HIP);
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(IBMI_ERR_HIP);
+  *out = P;
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_plan_blocks(ibmi_plan_t plan, int32_t* n_blocks, int64_t* bounds) {
+  if (!plan || !n_blocks) return IBMI_ERR_INVALID_ARG;
+  *n_blocks = (int32_t)plan->s.size();
+  if (bounds)
+    for (size_t k = 0; k < plan->s.size(); ++k) {
+      bounds[2 * k] = plan->s[k];
+      bounds[2 * k + 1] = plan->e[k];
+    }
+  return IBMI_OK;
+}
+
+static ibmi_status check_h(ibmi_plan_t plan, const double* dH, int64_t ldh) {
+  if (!plan || !dH || ldh < plan->p) return IBMI_ERR_INVALID_ARG;
+  const size_t h_bytes = (size_t)((plan->p - 1) * ldh + plan->p) * 8;
+  const size_t a_bytes = (size_t)((plan->p - 1) * plan->lda + plan->p) * 8;
+  if (ranges_overlap(dH, h_bytes, plan->A, a_bytes) ||
+      ranges_overlap(dH, h_bytes, plan->work, plan->L.total))
+    return IBMI_ERR_INVALID_ARG;
+  return IBMI_OK;
+}
+
+// Starts an event-bracketed region of category cat when profiling; returns the end event.
+static hipEvent_t prof_begin(ibmi_plan_t P, int cat) {
+  if (!P->profiling) return nullptr;
+  Timer& t = P->timers[cat];
+  hipEvent_t a = t.get(), b = t.get();
+  if (!a || !b) return nullptr;
+  (void)hipEventRecord(a, P->st);
+  t.pending.push_back({a, b});
+  return b;
+}
+static void prof_end(ibmi_plan_t P, int cat, hipEvent_t end, double flops) {
+  if (!end) return;
+  (void)hipEventRecord(end, P->st);
+  P->timers[cat].launches += 1;
+  P->timers[cat].flops += flops;
+}
+
+static ibmi_status block_step(ibmi_plan_t P, double* dH, int64_t ldh, int k) {
+  const BlockDesc& d = P->L.blocks[k];
+  const int64_t s = d.s, b = d.b, c = P->p - b;
+  hipStream_t st = P->st;
+  if (c == 0) {
+    IBMI_HIP(ibmi::copy_block(P->ainv(k), b, dH, ldh, s, st));
+    return IBMI_OK;
+  }
+  const IdxMap g{0, s, b};
+  Opnd Xw{P->wt(k), b, IdxMap{}, IdxMap{}};
+  Opnd Yp{dH, ldh, g, g};
+  hipEvent_t ev = prof_begin(P, 0);
+  IBMI_HIP(ibmi::gemm_panel(P->t.panel, Xw, Yp, b, c, c, dH, ldh, s, g, st));
+  prof_end(P, 0, ev, 2.0 * b * (double)c * c);
+  const int splits = diag_splits_for(b, c, P->t.diag, P->t.diag_splits);
+  Opnd Yd{dH, ldh, g, IdxMap{s, INT64_MAX, 0}};
+  ev = prof_begin(P, 1);
+  IBMI_HIP(ibmi::gemm_partial(P->t.diag, Xw, Yd, b, b, c, splits, P->part(), st));
+  IBMI_HIP(ibmi::diag_finalize(P->ainv(k), P->part(), splits, b, dH, ldh, s, st));
+  prof_end(P, 1, ev, 2.0 * (double)b * b * c);
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_block_step(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t k) {
+  ibmi_status rc = check_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  if (k < 0 || k >= (int32_t)plan->s.size()) return IBMI_ERR_INVALID_ARG;
+  return block_step(plan, dH, ldh, k);
+}
+
+ibmi_status ibmi_init_h(ibmi_plan_t plan, double* dH, int64_t ldh) {
+  ibmi_status rc = check_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  if (plan->o.init == IBMI_INIT_IDENTITY) {
+    IBMI_HIP(ibmi::fill_identity(dH, ldh, plan->p, 1.0, plan->st));
+  } else if (plan->o.init == IBMI_INIT_BLOCKDIAG_INV) {
+    IBMI_HIP(ibmi::fill_identity(dH, ldh, plan->p, 0.0, plan->st));
+    for (size_t k = 0; k < plan->s.size(); ++k)
+      IBMI_HIP(ibmi::copy_block(plan->ainv((int)k), plan->L.blocks[k].b, dH, ldh, plan->s[k],
+                                plan->st));
+  }
+  return IBMI_OK;
+}
+
+// Enqueue ||I - A H||_F^2 (scal[0]) and, if wanted, ||H||_F^2 (scal[1]); then read both.
+static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, bool want_h,
+                               double* res_sq, double* h_sq) {
+  hipStream_t st = P->st;
+  Opnd Xa{P->A, P->lda, IdxMap{}, IdxMap{}};
+  Opnd Yh{dH, ldh, IdxMap{}, IdxMap{}};
+  int64_t n_red = 0;
+  hipEvent_t ev = prof_begin(P, 2);
+  IBMI_HIP(ibmi::gemm_resid(P->t.resid, Xa, Yh, P->p, P->p, P->p, P->red(), &n_red, st));
+  IBMI_HIP(ibmi::reduce_sum(P->red(), n_red, P->scal(), st));
+  prof_end(P, 2, ev, 2.0 * (double)P->p * P->p * P->p);
+  if (want_h) {
+    int64_t n2 = 0;
+    IBMI_HIP(ibmi::sumsq(dH, ldh, P->p, P->red2(), &n2, st));
+    IBMI_HIP(ibmi::reduce_sum(P->red2(), n2, P->scal() + 1, st));
+  }
+  double host[2] = {0.0, 0.0};
+  IBMI_HIP(hipMemcpyAsync(host, P->scal(), sizeof(host), hipMemcpyDeviceToHost, st));
+  IBMI_HIP(hipStreamSynchronize(st));
+  if (P->profiling)
+    for (Timer& t : P->timers) t.collect();
+  *res_sq = host[0];
+  if (h_sq) *h_sq = host[1];
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, double* out) {
+  ibmi_status rc = check_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  if (!out) return IBMI_ERR_INVALID_ARG;
+  double r2 = 0.0;
+  rc = residual_sq(plan, dH, ldh, false, &r2, nullptr);
+  if (rc != IBMI_OK) return rc;
+  *out = std::sqrt(r2);
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* info,
+                       double* history) {
+  ibmi_status rc = check_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  if (!info) return IBMI_ERR_INVALID_ARG;
+  const ibmi_options& o = plan->o;
+  *info = ibmi_info{0, 0, -1, 0, 0.0, 0.0};
+  rc = ibmi_init_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  const int limit = o.fixed_sweeps > 0 ? o.fixed_sweeps : o.max_sweeps;
+  const bool want_h = o.stop == IBMI_STOP_REL_BOUND;
+  std::vector<double> hist;
+  const int K = (int)plan->s.size();
+  while (true) {
+    for (int k = 0; k < K; ++k) {
+      rc = block_step(plan, dH, ldh, k);
+      if (rc != IBMI_OK) return rc;
+    }
+    info->sweeps += 1;
+    double r2 = 0.0, h2 = 0.0;
+    rc = residual_sq(plan, dH, ldh, want_h, &r2, &h2);
+    if (rc != IBMI_OK) return rc;
+    const double rho = std::sqrt(r2);
+    info->residual = rho;
+    if (!std::isfinite(rho)) return IBMI_ERR_NONFINITE;
+    hist.push_back(rho);
+    if (history) history[info->sweeps - 1] = rho;
+    const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
+    info->stop_value = sv;
+    if (o.fixed_sweeps > 0) {
+      if (info->sweeps >= limit) {
+        info->converged = sv < o.tol;
+        break;
+      }
+      continue;
+    }
+    if (sv < o.tol) {
+      info->converged = 1;
+      break;
+    }
+    if (info->sweeps >= limit) break;
+    const size_t n = hist.size();
+    if (o.stagnation_guard && n >= 4 && rho < 100.0 * o.tol && hist[n - 1] > 0.99 * hist[n - 2] &&
+        hist[n - 2] > 0.99 * hist[n - 3] && hist[n - 3] > 0.99 * hist[n - 4]) {
+      info->floor_limited = 1;
+      break;
+    }
+  }
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_set_profiling(ibmi_plan_t plan, int32_t on) {
+  if (!plan) return IBMI_ERR_INVALID_ARG;
+  plan->profiling = on != 0;
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_kernel_times(ibmi_plan_t plan, double* ms, int64_t* launches, double* flops) {
+  if (!plan) return IBMI_ERR_INVALID_ARG;
+  IBMI_HIP(hipStreamSynchronize(plan->st));
+  for (int i = 0; i < 3; ++i) {
+    Timer& t = plan->timers[i];
+    t.collect();
+    if (ms) ms[i] = t.ms;
+    if (launches) launches[i] = t.launches;
+    if (flops) flops[i] = t.flops;
+    t.ms = 0.0;
+    t.flops = 0.0;
+    t.launches = 0;
+  }
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_plan_destroy(ibmi_plan_t plan) {
+  if (!plan) return IBMI_ERR_INVALID_ARG;
+  delete plan;
+  return IBMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal interface between the host driver (ibmi.cpp) and the gfx950 kernels
+// (kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibmi {
+
+// Index map j -> base + j + (j >= cut ? skip : 0).  Covers the identity (base 0, no cut),
+// a contiguous range I = [s, e) (base s) and a complement I^c = [0,s) u [e,p)
+// (base 0, cut s, skip e - s) without materialising index arrays or permutations.
+struct IdxMap {
+  int64_t base = 0, cut = INT64_MAX, skip = 0;
+  __host__ __device__ __forceinline__ int64_t operator()(int64_t j) const {
+    return base + j + (j >= cut ? skip : 0);
+  }
+};
+
+// Operand of the FP64 GEMM below: element (k, x) is ptr[r(k) * ld + c(x)].
+struct Opnd {
+  const double* ptr;
+  int64_t ld;
+  IdxMap r, c;
+};
+
+// Descriptor of one diagonal set I_k = [s, s + b) and where its factors live.
+struct BlockDesc {
+  int64_t s, b;
+  int64_t l_off;      // b*b: Cholesky factor, lower = L, strict upper = L^T
+  int64_t linv_off;   // b*b: L^{-1} (lower triangle, zeros above)
+  int64_t ainv_off;   // b*b: A_I^{-1}, bitwise symmetric
+};
+
+// Tile configurations of the FP64 MFMA GEMM.
+enum GemmCfg { GEMM_64x64 = 0, GEMM_128x128 = 1, GEMM_128x64 = 2, GEMM_CFG_COUNT = 3 };
+
+// C[m][n] = sum_{k in [k0, k0 + K)} X(k, m) * Y(k, n), for m < M, n < N.
+// Epilogues:
+//   store   : out[m * ldo + n] = C                                        (splits = 1)
+//   panel   : H[(s+m)*ldh + g(n)] = -C and H[g(n)*ldh + s+m] = -C          (splits = 1)
+//   partial : out[z * M * N + m * N + n] = C over K chunk z                (split-K)
+//   resid   : partial sums of (delta_mn - C)^2 per workgroup -> red[]      (splits = 1)
+hipError_t gemm_store(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                      double* out, int64_t ldo, hipStream_t st);
+hipError_t gemm_panel(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                      double* H, int64_t ldh, int64_t s, IdxMap g, hipStream_t st);
+hipError_t gemm_partial(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                        int splits, double* out, hipStream_t st);
+// Returns the number of partial sums written to red (one per workgroup slot).
+hipError_t gemm_resid(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                      double* red, int64_t* n_red, hipStream_t st);
+int64_t gemm_resid_slots(GemmCfg cfg, int64_t M, int64_t N);
+
+// Block factors (one launch for all sets of a plan).
+hipError_t chol_factor(const BlockDesc* d_desc, int n_blocks, int64_t b_max, const double* A,
+                       int64_t lda, double* fac, int* d_status, hipStream_t st);
+hipError_t chol_linv(const BlockDesc* d_desc, int n_blocks, int64_t b_max, double* fac,
+                     hipStream_t st);
+hipError_t symmetrize_block(const double* x, double* out, int64_t b, hipStream_t st);
+
+// H[I,I] = A_I^{-1} - (G + G^T)/2 with G = sum of `splits` partial b x b products.
+hipError_t diag_finalize(const double* ainv, const double* partial, int splits, int64_t b,
+                         double* H, int64_t ldh, int64_t s, hipStream_t st);
+
+// H = I, or H = 0 followed by copy_block for each set.
+hipError_t fill_identity(double* H, int64_t ldh, int64_t p, double diag, hipStream_t st);
+hipError_t copy_block(const double* src, int64_t b, double* H, int64_t ldh, int64_t s,
+                      hipStream_t st);
+
+// Sum of squares of H's entries, one partial per workgroup into red (returns count).
+hipError_t sumsq(const double* H, int64_t ldh, int64_t p, double* red, int64_t* n_red,
+                 hipStream_t st);
+// out[0] = sum red[0..n) in a fixed order (single workgroup).
+hipError_t reduce_sum(const double* red, int64_t n, double* out, hipStream_t st);
+hipError_t fill_int(int* p, int v, int n, hipStream_t st);
+
+}  // namespace ibmi

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point include/ibmi.h declares; host-only
+entry points (partitioner, workspace sizing, status strings) agree with the oracle.
+No device work is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ibmi.h")
+LIB = os.path.join(ROOT, "paper_2502_06377_amd", "libibmi.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibmi_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not os.path.exists(LIB):
+        pytest.fail("libibmi.so is not built (run python paper_2502_06377_amd/build.py)")
+    import paper_2502_06377_amd as m
+    return m
+
+
+def test_every_declared_symbol_is_exported(binding):
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.EXPORTED)
+
+
+@pytest.mark.parametrize("p,b,ovl", [(256, 128, 0), (4096, 576, 64), (16384, 576, 64), (100, 128, 16),
+                                     (230, 128, 16), (1000, 128, 16), (7, 3, 1), (8192, 576, 64)])
+def test_partition_matches_oracle(binding, p, b, ovl):
+    assert binding.ibmi_partition(p, b, ovl) == oracle.partition(p, b, ovl)
+
+
+def test_partition_sweep_matches_oracle(binding):
+    for p in range(1, 2100, 13):
+        for b, ovl in [(128, 16), (64, 0), (96, 31)]:
+            assert binding.ibmi_partition(p, b, ovl) == oracle.partition(p, b, ovl)
+
+
+def test_partition_rejects_bad_arguments(binding):
+    for args in [(0, 10, 0), (10, 0, 0), (10, 5, 5), (10, 5, -1)]:
+        with pytest.raises(binding.IbmiError):
+            binding.ibmi_partition(*args)
+
+
+def test_workspace_bytes(binding):
+    m = binding
+    ok = m.make_options(4096, 576, 64)
+    n = m.ibmi_workspace_bytes(ok)
+    # at least W^T (sum b c) and the three b x b factor blocks, in FP64
+    sets = oracle.partition(4096, 576, 64)
+    floor = sum(8 * ((e - s) * (4096 - (e - s)) + 3 * (e - s) ** 2) for s, e in sets)
+    assert n >= floor and n % 256 == 0
+    assert m.ibmi_workspace_bytes(m.make_options(4096, 576, 64, tol=-1.0)) == 0
+    assert m.ibmi_workspace_bytes(m.make_options(4096, 2048, 64)) == 0          # sets > 1024 rows
+    assert m.ibmi_workspace_bytes(m.make_options(100, bounds=[(0, 50), (60, 100)])) == 0  # gap
+    assert m.ibmi_workspace_bytes(m.make_options(100, bounds=[(50, 100), (0, 60)])) == 0  # unsorted
+    assert m.ibmi_workspace_bytes(m.make_options(100, bounds=[(0, 60), (50, 100)],
+                                                 init="blockdiag_inv")) == 0
+    assert m.ibmi_workspace_bytes(m.make_options(100, bounds=[(0, 60), (50, 100)])) > 0
+
+
+def test_status_strings(binding):
+    assert binding.ibmi_status_str(0) == "IBMI_OK"
+    assert binding.ibmi_status_str(2) == "IBMI_ERR_NOT_SPD"
+    assert binding.ibmi_status_str(99) == "IBMI_UNKNOWN_STATUS"
