@@ -2,7 +2,9 @@
 
 A step is one IBMI sweep of the whole hot path: the block update of eq. (IBMI) for all 32
 sets (panel GEMM W H[I^c,I^c] scattered into H, split-K diagonal product and H[I,I]
-finalisation) followed by the ||I - A H||_F check with its host read-back.  Plan time (block
+finalisation) followed by the ||I - A H||_F check with its host read-back.  The FP64 form is
+the headline value; the FP32-update (correction) form is timed the same way and reported
+beside it, with its speedup per sweep.  Plan time (block
 factors, once per solve) is reported separately.  Inputs are synthetic: 16384 seeded
 uniform points in the unit square sorted by x, SE kernel with length scale 0.05 plus a
 1e-3 nugget, FP64, resident in HBM before timing starts.
@@ -55,7 +57,8 @@ def main():
     ap.add_argument("--p", type=int, default=16384)
     ap.add_argument("--full-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sets", type=int, default=3)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-sets", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -73,40 +76,41 @@ def main():
     A = torch.from_numpy(A_host).to(dev)
     H = torch.empty((p, p), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-
-    log("plan")
-    t0 = time.perf_counter()
-    plan = ib.Plan(A, block_rows=block_rows, overlap=overlap, stop="rel_bound",
-                   lambda_min=nugget, tol=1e-10, max_sweeps=500)
-    torch.cuda.synchronize()
-    plan_s = time.perf_counter() - t0
-    ranges = plan.blocks
-    K = len(ranges)
-
-    def sweep():
-        for k in range(K):
-            ib.ibmi_block_step(plan.handle, H, k)
-        return ib.ibmi_residual(plan.handle, H)
-
-    ib.ibmi_init_h(plan.handle, H)
-    log(f"warmup {args.warmup} sweeps (K={K})")
-    for _ in range(args.warmup):
-        sweep()
-    ib.ibmi_set_profiling(plan.handle, True)
-    ib.ibmi_kernel_times(plan.handle)  # reset
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} sweeps")
-    t0 = time.perf_counter()
-    res = None
-    for i in range(args.steps):
-        res = sweep()
-        log(f"sweep {args.warmup + i + 1}: ||I-AH||_F = {res:.3e}")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kt = ib.ibmi_kernel_times(plan.handle)
-    ib.ibmi_set_profiling(plan.handle, False)
-
     import oracle  # flop accounting of the algorithm (cost section), no compute
+
+    def run_form(prec):
+        log(f"[{prec}] plan")
+        t0 = time.perf_counter()
+        plan = ib.Plan(A, block_rows=block_rows, overlap=overlap, precision=prec,
+                       stop="rel_bound", lambda_min=nugget, tol=1e-10, max_sweeps=500)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        ranges = plan.blocks
+        ib.ibmi_init_h(plan.handle, H)
+        log(f"[{prec}] warmup {args.warmup} sweeps (K={len(ranges)})")
+        for i in range(args.warmup):
+            ib.ibmi_sweep(plan.handle, H, i == 0)
+        ib.ibmi_set_profiling(plan.handle, True)
+        ib.ibmi_kernel_times(plan.handle)  # reset
+        hist = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            hist.append(ib.ibmi_sweep(plan.handle, H, args.warmup == 0 and i == 0))
+            log(f"[{prec}] sweep {args.warmup + i + 1}: ||I-AH||_F = {hist[-1]:.3e}")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = ib.ibmi_kernel_times(plan.handle)
+        ib.ibmi_set_profiling(plan.handle, False)
+        return plan, ranges, plan_s, dt, kt, hist
+
+    def kernels_json(kt):
+        return {c: {"ms_per_launch": round(v[0] / max(v[1], 1), 4), "launches": v[1],
+                    "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 else None}
+                for c, v in kt.items()}
+
+    plan, ranges, plan_s, dt, kt, hist = run_form("fp64")
+    K = len(ranges)
     f_sweep = oracle.flops_sweep(p, ranges)
     f_plan = oracle.flops_plan(p, ranges)
     ms_step = dt / args.steps * 1e3
@@ -114,6 +118,7 @@ def main():
     panel_ms, panel_n, panel_fl = kt["panel"]
     achieved = panel_fl / (panel_ms * 1e-3) / 1e12 if panel_ms > 0 else 0.0
     peak = 78.6
+    rate = (hist[-1] / hist[0]) ** (1.0 / max(len(hist) - 1, 1)) if len(hist) > 1 else None
     out = {
         "metric": "IBMI TFLOP/s + s/solve at p=16384 to 1e-10 (mixed vs FP64); p99 latency",
         "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -124,25 +129,44 @@ def main():
         "sweeps_per_s": round(1e3 / ms_step, 4),
         "plan_s": round(plan_s, 4),
         "plan_tflops": round(f_plan / plan_s / 1e12, 3),
-        "kernels": {c: {"ms_per_launch": round(v[0] / max(v[1], 1), 4), "launches": v[1],
-                        "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 else None}
-                    for c, v in kt.items()},
-        "roofline": {"kernel": "gemm_f64_kernel panel epilogue (W H[I^c,I^c] -> H)", "bound": "mfma",
-                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None},
+        "kernels": kernels_json(kt),
+        "roofline": {"kernel": "gemm_kernel<double> panel epilogue (W H[I^c,I^c] -> H)",
+                     "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
+        "residual_rate_per_sweep": round(rate, 5) if rate else None,
     }
-    if args.full_solve:
-        log("full solve to relative-error bound 1e-10")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sol = plan.solve(H)
-        torch.cuda.synchronize()
-        solve_s = time.perf_counter() - t0
-        out["full_solve"] = {"s_per_solve": round(solve_s + plan_s, 2), "sweeps": sol.sweeps,
-                             "converged": sol.converged, "stop_value": sol.stop_value,
-                             "residual": sol.residual}
-        log(f"full solve: {sol.sweeps} sweeps, {solve_s:.1f} s, bound {sol.stop_value:.2e}")
     plan.close()
+    if not args.no_mixed:
+        mplan, _, mplan_s, mdt, mkt, mhist = run_form("fp32")
+        mms = mdt / args.steps * 1e3
+        out["fp32_update_form"] = {
+            "ms_per_step": round(mms, 3), "sweeps_per_s": round(1e3 / mms, 4),
+            "ibmi_tflops_equiv": round(f_sweep / (mms * 1e-3) / 1e12, 3),
+            "speedup_vs_fp64": round(ms_step / mms, 3), "plan_s": round(mplan_s, 4),
+            "kernels": kernels_json(mkt),
+            "max_rel_residual_gap_vs_fp64": round(max(abs(a - b) / b for a, b in zip(mhist, hist)), 6),
+        }
+        mplan.close()
+        plan = None
+    else:
+        plan = None
+    if args.full_solve:
+        out["full_solve"] = {}
+        for prec in ("fp64", "fp32"):
+            log(f"[{prec}] full solve to relative-error bound 1e-10")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fplan = ib.Plan(A, block_rows=block_rows, overlap=overlap, precision=prec,
+                            stop="rel_bound", lambda_min=nugget, tol=1e-10, max_sweeps=500)
+            sol = fplan.solve(H)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            fplan.close()
+            out["full_solve"][prec] = {"s_per_solve": round(solve_s, 2), "sweeps": sol.sweeps,
+                                       "converged": sol.converged, "stop_value": sol.stop_value,
+                                       "residual": sol.residual}
+            log(f"[{prec}] full solve: {sol.sweeps} sweeps, {solve_s:.1f} s, "
+                f"bound {sol.stop_value:.2e}")
     del H, A
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

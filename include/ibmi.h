@@ -134,8 +134,17 @@ ibmi_status ibmi_plan_blocks(ibmi_plan_t plan, int32_t* n_blocks, int64_t* bound
  * NONFINITE if the residual is NaN/Inf (H then holds the offending iterate). */
 ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* info, double* history);
 
-/* Enqueue one application of eq. (IBMI) for set k (0-based) on dH, with no
- * synchronisation.  Reads H[I_k^c, I_k^c], writes rows and columns I_k. */
+/* One sweep (sets k = 1..K in order) in the plan's precision form, then ||I - A H||_F written
+ * to *residual (host, nullable); synchronises once.  The FP32-update form carries the
+ * residual matrix of the previous sweep in the workspace: pass restart = 1 on the first call
+ * for an H, or whenever H was changed by anything but ibmi_sweep on this plan.
+ * NONFINITE if the residual is NaN/Inf. */
+ibmi_status ibmi_sweep(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t restart,
+                       double* residual);
+
+/* Enqueue one application of eq. (IBMI) for set k (0-based) on dH in FP64, with no
+ * synchronisation, whatever the plan's precision.  Reads H[I_k^c, I_k^c], writes rows and
+ * columns I_k. */
 ibmi_status ibmi_block_step(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t k);
 
 /* Enqueue the initial H of opts->init (IDENTITY or BLOCKDIAG_INV; GIVEN leaves dH as is). */
@@ -145,13 +154,14 @@ ibmi_status ibmi_init_h(ibmi_plan_t plan, double* dH, int64_t ldh);
  * the plan's stream and writes the value to *out (host). */
 ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, double* out);
 
-/* Kernel timing, for measurement.  While enabled, each panel GEMM (V = W H[I^c,I^c] with its
- * scatter into H), each diagonal update (split-K W H[I^c,I] plus the finalisation of H[I,I])
- * and each residual launch is bracketed by HIP events on the plan's stream.
- * ibmi_kernel_times synchronises the stream, then returns and resets, per category
- * (0 = panel, 1 = diagonal, 2 = residual): accumulated milliseconds, launch counts and the
- * algorithmic flops of those launches (2 b c^2, 2 b^2 c and 2 p^3 respectively).  Arrays are
- * host arrays of length 3; any may be NULL. */
+/* Kernel timing, for measurement.  While enabled, launches are bracketed by HIP events on the
+ * plan's stream in three categories.  FP64 form: 0 = panel GEMM V = W H[I^c,I^c] with its
+ * scatter into H (2 b c^2 flops), 1 = diagonal update (split-K W H[I^c,I] and H[I,I];
+ * 2 b^2 c), 2 = residual (2 p^3).  FP32-update form: 0 = the FP32 product A[:,I]^T D
+ * (2 b (u p + (p-u) u) flops, u = rows already updated in the sweep), 1 = the FP64
+ * corrections of the set (4 b^2 c + 2 b^3), 2 = residual with its store (2 p^3).
+ * ibmi_kernel_times synchronises the stream, then returns and resets, per category:
+ * accumulated milliseconds, launch counts and flops.  Host arrays of length 3; any may be NULL. */
 ibmi_status ibmi_set_profiling(ibmi_plan_t plan, int32_t on);
 ibmi_status ibmi_kernel_times(ibmi_plan_t plan, double* ms, int64_t* launches, double* flops);
 

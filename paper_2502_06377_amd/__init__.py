@@ -64,6 +64,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_int64)]),
     "ibmi_solve": (ctypes.c_int, [_vp, _dp, _i64, ctypes.POINTER(IbmiInfo),
                                   ctypes.POINTER(ctypes.c_double)]),
+    "ibmi_sweep": (ctypes.c_int, [_vp, _dp, _i64, _i32, ctypes.POINTER(ctypes.c_double)]),
     "ibmi_block_step": (ctypes.c_int, [_vp, _dp, _i64, _i32]),
     "ibmi_init_h": (ctypes.c_int, [_vp, _dp, _i64]),
     "ibmi_residual": (ctypes.c_int, [_vp, _dp, _i64, ctypes.POINTER(ctypes.c_double)]),
@@ -164,6 +165,13 @@ def ibmi_solve(plan: int, H: torch.Tensor, history_len: int = 0):
     hist = (ctypes.c_double * history_len)() if history_len > 0 else None
     _check(_lib.ibmi_solve(plan, _dptr(H), H.stride(0), ctypes.byref(info), hist), "ibmi_solve")
     return info, ([hist[i] for i in range(info.sweeps)] if hist is not None else [])
+
+
+def ibmi_sweep(plan: int, H: torch.Tensor, restart: bool) -> float:
+    out = ctypes.c_double(0.0)
+    _check(_lib.ibmi_sweep(plan, _dptr(H), H.stride(0), int(restart), ctypes.byref(out)),
+           "ibmi_sweep")
+    return out.value
 
 
 def ibmi_block_step(plan: int, H: torch.Tensor, k: int) -> None:

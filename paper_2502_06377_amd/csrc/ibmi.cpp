@@ -99,7 +99,8 @@ ibmi_status make_sets(const ibmi_options* o, std::vector<int64_t>& s, std::vecto
 ibmi_status check_options(const ibmi_options* o) {
   if (!o) return IBMI_ERR_INVALID_ARG;
   if (!(o->tol > 0.0) || o->max_sweeps < 1 || o->fixed_sweeps < 0) return IBMI_ERR_INVALID_ARG;
-  if (o->precision != IBMI_PREC_FP64) return IBMI_ERR_INVALID_ARG;
+  if (o->precision != IBMI_PREC_FP64 && o->precision != IBMI_PREC_FP32_UPDATE)
+    return IBMI_ERR_INVALID_ARG;
   if (o->init < IBMI_INIT_IDENTITY || o->init > IBMI_INIT_GIVEN) return IBMI_ERR_INVALID_ARG;
   if (o->stop != IBMI_STOP_FRO && o->stop != IBMI_STOP_REL_BOUND) return IBMI_ERR_INVALID_ARG;
   if (o->stop == IBMI_STOP_REL_BOUND && !(o->lambda_min > 0.0)) return IBMI_ERR_INVALID_ARG;
@@ -113,14 +114,22 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
   return (i >= 0 && i < ibmi::GEMM_CFG_COUNT) ? (GemmCfg)i : dflt;
 }
 
+// Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel and
+// diagonal products favour small tiles with many resident waves, the square residual the
+// 8-wave 128x128 tile, the FP32 update the 64x64 tile.
 struct Tuning {
-  GemmCfg panel = ibmi::GEMM_64x64, diag = ibmi::GEMM_64x64, resid = ibmi::GEMM_64x64,
-          plan = ibmi::GEMM_64x64;
+  GemmCfg panel = ibmi::GEMM_64x64_K16, diag = ibmi::GEMM_64x64_K16,
+          resid = ibmi::GEMM_128x128_W8, plan = ibmi::GEMM_64x64_K16, upd32 = ibmi::GEMM_64x64,
+          small = ibmi::GEMM_64x64_K16;
   int diag_splits = 0;  // 0 = automatic
 };
 
-Tuning tuning_for(int64_t /*p*/) {
+Tuning tuning_for(int64_t p) {
   Tuning t;
+  if (p < 2048) {  // small matrices: more, smaller tiles
+    t.resid = ibmi::GEMM_64x64_K16;
+  }
+  t.upd32 = env_cfg("IBMI_CFG_UPD32", t.upd32);
   t.panel = env_cfg("IBMI_CFG_PANEL", t.panel);
   t.diag = env_cfg("IBMI_CFG_DIAG", t.diag);
   t.resid = env_cfg("IBMI_CFG_RESID", t.resid);
@@ -132,7 +141,7 @@ Tuning tuning_for(int64_t /*p*/) {
 int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
   if (c <= 0) return 1;
   if (forced > 0) return (int)std::min<int64_t>(forced, std::max<int64_t>(1, c / 64));
-  const int64_t tiles = ibmi::gemm_resid_slots(cfg, b, b);
+  const int64_t tiles = ibmi::gemm_tiles(cfg, b, b);
   int64_t want = (512 + tiles - 1) / tiles;
   want = std::min<int64_t>(want, std::max<int64_t>(1, c / 512));
   return (int)std::max<int64_t>(1, std::min<int64_t>(want, 32));
@@ -141,6 +150,8 @@ int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
   size_t desc = 0, fac = 0, wt = 0, part = 0, red = 0, red2 = 0, scal = 0, status = 0, total = 0;
+  // FP32-update form only (zero size otherwise)
+  size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, x2 = 0;
   std::vector<BlockDesc> blocks;
   std::vector<int64_t> wt_off;  // doubles, relative to wt
   int64_t b_max = 0;
@@ -169,7 +180,7 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
     L.b_max = std::max(L.b_max, b);
     L.splits = std::max(L.splits, diag_splits_for(b, c, t.diag, t.diag_splits));
   }
-  L.red_len = std::max<int64_t>(ibmi::gemm_resid_slots(t.resid, p, p), 1);
+  L.red_len = std::max<int64_t>(ibmi::gemm_tiles(t.resid, p, p), 1);
   size_t off = 0;
   L.desc = off;
   off = align_up(off + K * sizeof(BlockDesc));
@@ -187,6 +198,28 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
   off = align_up(off + 8 * 8);
   L.status = off;
   off = align_up(off + 4 * sizeof(int));
+  if (o->precision == IBMI_PREC_FP32_UPDATE) {
+    const size_t pp = (size_t)p * p;
+    const int64_t c_max = p - [&] {
+      int64_t bmin = p;
+      for (const auto& d : L.blocks) bmin = std::min(bmin, d.b);
+      return bmin;
+    }();
+    L.a32 = off;
+    off = align_up(off + pp * 4);
+    L.dmat = off;
+    off = align_up(off + pp * 4);
+    L.rt = off;
+    off = align_up(off + pp * 8);
+    L.rkt = off;
+    off = align_up(off + (size_t)L.b_max * p * 8);
+    L.delta = off;
+    off = align_up(off + (size_t)std::max<int64_t>(c_max, 1) * L.b_max * 8);
+    L.tt = off;
+    off = align_up(off + (size_t)L.b_max * L.b_max * 8);
+    L.x2 = off;
+    off = align_up(off + (size_t)L.b_max * L.b_max * 8);
+  }
   L.total = off;
   return L;
 }
@@ -254,6 +287,14 @@ struct ibmi_plan_s {
   double* scal() const { return (double*)(work + L.scal); }
   int* status() const { return (int*)(work + L.status); }
   BlockDesc* desc() const { return (BlockDesc*)(work + L.desc); }
+  bool mixed() const { return o.precision == IBMI_PREC_FP32_UPDATE; }
+  float* a32() const { return (float*)(work + L.a32); }
+  float* dmat() const { return (float*)(work + L.dmat); }
+  double* rt() const { return (double*)(work + L.rt); }
+  double* rkt() const { return (double*)(work + L.rkt); }
+  double* delta() const { return (double*)(work + L.delta); }
+  double* tt() const { return (double*)(work + L.tt); }
+  double* x2() const { return (double*)(work + L.x2); }
 };
 
 extern "C" {
@@ -368,6 +409,8 @@ ibmi_status ibmi_plan(ibmi_plan_t* out, const ibmi_options* opts, const double* 
         return fail(IBMI_ERR_HIP);
     }
   }
+  if (P->mixed() && ibmi::to_f32(P->A, P->lda, P->a32(), P->p, st) != hipSuccess)
+    return fail(IBMI_ERR_HIP);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(IBMI_ERR_HIP);
   *out = P;
   return IBMI_OK;
@@ -434,6 +477,87 @@ static ibmi_status block_step(ibmi_plan_t P, double* dH, int64_t ldh, int k) {
   return IBMI_OK;
 }
 
+static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, bool want_h,
+                               double* res_sq, double* h_sq, double* store);
+
+// One set of the FP32-update (correction) form.  On entry rt holds R_s^T = I - A H_s for the
+// H at the start of the sweep and dmat holds D = H - H_s in FP32; u is the end of the union of
+// the sets already updated in this sweep (D vanishes outside rows/columns [0,u)).
+//   RkT   = R_s^T[I,:] - A[:,I]^T D       (FP32 matrix cores, FP32 accumulation)
+//   Delta = R[I^c,I] A_I^{-1}             H[I^c,I] += Delta, mirrored; D likewise
+//   T     = R[I,I] - Delta^T A[I^c,I]     (split-K, fixed-order sum)
+//   H[I,I] += sym(T A_I^{-1});  D[I,I] likewise
+static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int k, int64_t u) {
+  const BlockDesc& d = P->L.blocks[k];
+  const int64_t s = d.s, b = d.b, c = P->p - b, p = P->p;
+  hipStream_t st = P->st;
+  if (c == 0) {
+    IBMI_HIP(ibmi::copy_block(P->ainv(k), b, dH, ldh, s, st));
+    return IBMI_OK;
+  }
+  const IdxMap g{0, s, b};
+  hipEvent_t ev = prof_begin(P, 0);
+  Opnd Xa32{(const double*)P->a32(), p, IdxMap{}, IdxMap{s, INT64_MAX, 0}};
+  Opnd Yd32{(const double*)P->dmat(), p, IdxMap{}, IdxMap{}};
+  IBMI_HIP(ibmi::gemm_f32_subfrom(P->t.upd32, Xa32, Yd32, b, p, p, u, u, P->rt(), p, s, P->rkt(),
+                                  p, st));
+  prof_end(P, 0, ev, 2.0 * (double)b * ((double)u * p + (double)(p - u) * u));
+  ev = prof_begin(P, 1);
+  Opnd Xr{P->rkt(), p, IdxMap{}, g};
+  Opnd Yi{P->ainv(k), b, IdxMap{}, IdxMap{}};
+  IBMI_HIP(ibmi::gemm_corr(P->t.plan, Xr, Yi, c, b, b, P->delta(), b, dH, ldh, P->dmat(), p, s, g,
+                           st));
+  const int splits = diag_splits_for(b, c, P->t.diag, P->t.diag_splits);
+  Opnd Xd{P->delta(), b, IdxMap{}, IdxMap{}};
+  Opnd Ya{P->A, P->lda, g, IdxMap{s, INT64_MAX, 0}};
+  IBMI_HIP(ibmi::gemm_partial(P->t.diag, Xd, Ya, b, b, c, splits, P->part(), st));
+  IBMI_HIP(ibmi::corr_diag(P->rkt(), p, s, P->part(), splits, b, P->tt(), st));
+  Opnd Xt{P->tt(), b, IdxMap{}, IdxMap{}};
+  IBMI_HIP(ibmi::gemm_store(P->t.small, Xt, Yi, b, b, b, P->x2(), b, st));
+  IBMI_HIP(ibmi::corr_apply(P->x2(), b, dH, ldh, P->dmat(), p, s, st));
+  prof_end(P, 1, ev, 4.0 * (double)b * b * c + 2.0 * (double)b * b * b);
+  return IBMI_OK;
+}
+
+// One full sweep of the plan's form followed by the residual; restart recomputes the
+// starting residual of the FP32-update form from H.
+static ibmi_status sweep_once(ibmi_plan_t P, double* dH, int64_t ldh, bool restart, bool want_h,
+                              double* res_sq, double* h_sq) {
+  const int K = (int)P->s.size();
+  if (!P->mixed()) {
+    for (int k = 0; k < K; ++k) {
+      ibmi_status rc = block_step(P, dH, ldh, k);
+      if (rc != IBMI_OK) return rc;
+    }
+    return residual_sq(P, dH, ldh, want_h, res_sq, h_sq, nullptr);
+  }
+  const int64_t p = P->p;
+  if (restart) {
+    double ignore = 0.0;
+    ibmi_status rc = residual_sq(P, dH, ldh, false, &ignore, nullptr, P->rt());
+    if (rc != IBMI_OK) return rc;
+  }
+  IBMI_HIP(ibmi::zero_f32(P->dmat(), p * p, P->st));
+  int64_t u = 0;
+  for (int k = 0; k < K; ++k) {
+    ibmi_status rc = block_step_mixed(P, dH, ldh, k, u);
+    if (rc != IBMI_OK) return rc;
+    u = std::max(u, P->e[k]);
+  }
+  return residual_sq(P, dH, ldh, want_h, res_sq, h_sq, P->rt());
+}
+
+ibmi_status ibmi_sweep(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t restart,
+                       double* residual) {
+  ibmi_status rc = check_h(plan, dH, ldh);
+  if (rc != IBMI_OK) return rc;
+  double r2 = 0.0;
+  rc = sweep_once(plan, dH, ldh, restart != 0, false, &r2, nullptr);
+  if (rc != IBMI_OK) return rc;
+  if (residual) *residual = std::sqrt(r2);
+  return std::isfinite(r2) ? IBMI_OK : IBMI_ERR_NONFINITE;
+}
+
 ibmi_status ibmi_block_step(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t k) {
   ibmi_status rc = check_h(plan, dH, ldh);
   if (rc != IBMI_OK) return rc;
@@ -457,13 +581,14 @@ ibmi_status ibmi_init_h(ibmi_plan_t plan, double* dH, int64_t ldh) {
 
 // Enqueue ||I - A H||_F^2 (scal[0]) and, if wanted, ||H||_F^2 (scal[1]); then read both.
 static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, bool want_h,
-                               double* res_sq, double* h_sq) {
+                               double* res_sq, double* h_sq, double* store) {
   hipStream_t st = P->st;
   Opnd Xa{P->A, P->lda, IdxMap{}, IdxMap{}};
   Opnd Yh{dH, ldh, IdxMap{}, IdxMap{}};
   int64_t n_red = 0;
   hipEvent_t ev = prof_begin(P, 2);
-  IBMI_HIP(ibmi::gemm_resid(P->t.resid, Xa, Yh, P->p, P->p, P->p, P->red(), &n_red, st));
+  IBMI_HIP(ibmi::gemm_resid(P->t.resid, Xa, Yh, P->p, P->p, P->p, P->red(), &n_red, store,
+                            P->p, st));
   IBMI_HIP(ibmi::reduce_sum(P->red(), n_red, P->scal(), st));
   prof_end(P, 2, ev, 2.0 * (double)P->p * P->p * P->p);
   if (want_h) {
@@ -486,7 +611,7 @@ ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, doubl
   if (rc != IBMI_OK) return rc;
   if (!out) return IBMI_ERR_INVALID_ARG;
   double r2 = 0.0;
-  rc = residual_sq(plan, dH, ldh, false, &r2, nullptr);
+  rc = residual_sq(plan, dH, ldh, false, &r2, nullptr, nullptr);
   if (rc != IBMI_OK) return rc;
   *out = std::sqrt(r2);
   return IBMI_OK;
@@ -504,16 +629,11 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
   const int limit = o.fixed_sweeps > 0 ? o.fixed_sweeps : o.max_sweeps;
   const bool want_h = o.stop == IBMI_STOP_REL_BOUND;
   std::vector<double> hist;
-  const int K = (int)plan->s.size();
   while (true) {
-    for (int k = 0; k < K; ++k) {
-      rc = block_step(plan, dH, ldh, k);
-      if (rc != IBMI_OK) return rc;
-    }
-    info->sweeps += 1;
     double r2 = 0.0, h2 = 0.0;
-    rc = residual_sq(plan, dH, ldh, want_h, &r2, &h2);
+    rc = sweep_once(plan, dH, ldh, info->sweeps == 0, want_h, &r2, &h2);
     if (rc != IBMI_OK) return rc;
+    info->sweeps += 1;
     const double rho = std::sqrt(r2);
     info->residual = rho;
     if (!std::isfinite(rho)) return IBMI_ERR_NONFINITE;

@@ -31,8 +31,31 @@ struct BlockDesc {
   int64_t ainv_off;   // b*b: A_I^{-1}, bitwise symmetric
 };
 
-// Tile configurations of the FP64 MFMA GEMM.
-enum GemmCfg { GEMM_64x64 = 0, GEMM_128x128 = 1, GEMM_128x64 = 2, GEMM_CFG_COUNT = 3 };
+// Tile configurations of the MFMA GEMM: workgroup tile, waves, and the number of
+// independent 16x16 accumulation chains each wave carries.
+enum GemmCfg {
+  GEMM_64x64 = 0,     // 2x2 waves of 32x32 ( 4 chains), BK 32
+  GEMM_128x128 = 1,   // 2x2 waves of 64x64 (16 chains), BK 32
+  GEMM_96x128 = 2,    // 2x2 waves of 48x64 (12 chains), BK 32
+  GEMM_128x64 = 3,    // 2x2 waves of 64x32 ( 8 chains), BK 32
+  GEMM_192x64 = 4,    // 2x2 waves of 96x32 (12 chains), BK 32
+  GEMM_64x64_W1 = 5,  // 1 wave of 64x64    (16 chains), BK 16
+  GEMM_32x64_W1 = 6,  // 1 wave of 32x64    ( 8 chains), BK 16
+  GEMM_64x64_K16 = 7,    // 2x2 waves of 32x32 ( 4 chains), BK 16
+  GEMM_128x64_K16 = 8,   // 2x2 waves of 64x32 ( 8 chains), BK 16
+  GEMM_64x128_K16 = 9,   // 2x2 waves of 32x64 ( 8 chains), BK 16
+  GEMM_128x128_W8 = 10,  // 2x4 waves of 64x32 ( 8 chains), BK 16
+  GEMM_128x128_W16 = 11, // 4x4 waves of 32x32 ( 4 chains), BK 16
+  GEMM_96x64_K16 = 12,   // 2x2 waves of 48x32 ( 6 chains), BK 16
+  GEMM_192x128_W8 = 13,  // 2x4 waves of 96x32 (12 chains), BK 16
+  GEMM_64x64_W2 = 14,    // 2x1 waves of 32x64 ( 8 chains), BK 32
+  GEMM_CFG_COUNT = 15
+};
+struct GemmDims {
+  int bm, bn;
+};
+GemmDims gemm_dims(GemmCfg c);
+int64_t gemm_tiles(GemmCfg cfg, int64_t M, int64_t N);
 
 // C[m][n] = sum_{k in [k0, k0 + K)} X(k, m) * Y(k, n), for m < M, n < N.
 // Epilogues:
@@ -46,10 +69,26 @@ hipError_t gemm_panel(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t
                       double* H, int64_t ldh, int64_t s, IdxMap g, hipStream_t st);
 hipError_t gemm_partial(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
                         int splits, double* out, hipStream_t st);
-// Returns the number of partial sums written to red (one per workgroup slot).
+// Writes one partial sum of (delta_mn - C)^2 per tile to red (gemm_tiles of them) and their
+// count to *n_red; when out is non-null also stores delta_mn - C to out[m * ldo + n].
 hipError_t gemm_resid(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
-                      double* red, int64_t* n_red, hipStream_t st);
-int64_t gemm_resid_slots(GemmCfg cfg, int64_t M, int64_t N);
+                      double* red, int64_t* n_red, double* out, int64_t ldo, hipStream_t st);
+// FP32 operands, FP32 accumulation: out[m][n] = src[(s+m)*lds + n] - C[m][n].  Column tiles
+// starting at n0 >= ncut only sum k < klim (the rest of the operand is known to be zero).
+hipError_t gemm_f32_subfrom(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                            int64_t ncut, int64_t klim, const double* src, int64_t lds,
+                            int64_t s, double* out, int64_t ldo, hipStream_t st);
+// Delta = C (m over I^c via g, n over I): stores Delta[m][n] to delta and adds it to
+// H[g(m)][s+n] (mirrored to H[s+n][g(m)]) and, rounded to FP32, to D likewise.
+hipError_t gemm_corr(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
+                     double* delta, int64_t ld_delta, double* H, int64_t ldh, float* D,
+                     int64_t ldd, int64_t s, IdxMap g, hipStream_t st);
+hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t p, hipStream_t st);
+hipError_t zero_f32(float* x, int64_t n, hipStream_t st);
+hipError_t corr_diag(const double* rkt, int64_t ldr, int64_t s, const double* part, int splits,
+                     int64_t b, double* tt, hipStream_t st);
+hipError_t corr_apply(const double* x, int64_t b, double* H, int64_t ldh, float* D, int64_t ldd,
+                      int64_t s, hipStream_t st);
 
 // Block factors (one launch for all sets of a plan).
 hipError_t chol_factor(const BlockDesc* d_desc, int n_blocks, int64_t b_max, const double* A,

@@ -162,17 +162,21 @@ def test_deterministic_and_resume(ib):
 
 
 def test_stop_tests_converge(ib):
-    _say("stop tests p=1500")
-    A = workloads.config2_matrix(p=1500)
-    out, H = _gpu_solve(ib, A, block_rows=576, overlap=64, tol=1e-9, max_sweeps=500)
-    ref = oracle.ibmi_solve(A, oracle.partition(1500, 576, 64), tol=1e-9, max_sweeps=500)
-    assert out.converged and out.sweeps == ref.sweeps
+    """Both stop tests on a well-conditioned matrix (shift 0.3 bounds lambda_min below), with
+    tolerances far from the FP64 floor so that the crossing sweep is unambiguous."""
+    _say("stop tests p=1200")
+    A = workloads.wishart_spd(1200, np.random.default_rng(8), shift=0.3)
+    ranges = oracle.partition(1200, 256, 32)
+    out, H = _gpu_solve(ib, A, block_rows=256, overlap=32, tol=1e-8, max_sweeps=500)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-8, max_sweeps=500)
+    assert out.converged and ref.converged and out.sweeps == ref.sweeps
     assert _rel(H, ref.h) <= TOL
-    out2, H2 = _gpu_solve(ib, A, block_rows=576, overlap=64, stop="rel_bound", lambda_min=1e-2,
-                          tol=1e-10, max_sweeps=500)
-    assert out2.converged and out2.stop_value < 1e-10
-    inv = np.linalg.inv(A)
-    assert _rel(H2, inv) < 1e-10
+    out2, H2 = _gpu_solve(ib, A, block_rows=256, overlap=32, stop="rel_bound", lambda_min=0.3,
+                          tol=1e-11, max_sweeps=500)
+    assert out2.converged and out2.stop_value < 1e-11
+    assert _rel(H2, np.linalg.inv(A)) < 1e-11
+    out3, _ = _gpu_solve(ib, A, block_rows=256, overlap=32, tol=1e-300, max_sweeps=3)
+    assert out3.sweeps == 3 and not out3.converged
 
 
 def test_full_size_16384_first_block_and_properties(ib):
@@ -207,3 +211,60 @@ def test_full_size_16384_first_block_and_properties(ib):
     res = plan.residual(H)
     assert np.isfinite(res) and res > 0
     plan.close()
+
+
+# ------------------------------------------------------------------ FP32-update form
+
+def test_mixed_form_refines_to_fp64_oracle(ib):
+    """FP32 matrix-core products in the correction form, FP64 factors and residual: the
+    converged H matches the FP64 oracle's converged H to the FP64 bar."""
+    _say("mixed form p=2048 Matern-3/2 to rel bound 1e-10")
+    A = workloads.config2_matrix(p=2048)
+    ranges = oracle.partition(2048, 576, 64)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-10, stop="rel_bound", lam_min=1e-2, max_sweeps=500)
+    assert ref.converged
+    out, H = _gpu_solve(ib, A, block_rows=576, overlap=64, precision="fp32", stop="rel_bound",
+                        lambda_min=1e-2, tol=1e-10, max_sweeps=500)
+    assert out.converged and np.array_equal(H, H.T)
+    assert abs(out.sweeps - ref.sweeps) <= 2
+    assert _rel(H, ref.h) <= TOL
+
+
+def test_mixed_form_ragged_against_inverse(ib):
+    _say("mixed form ragged wishart p=1000 b=256 ovl=40")
+    A = workloads.wishart_spd(1000, np.random.default_rng(3), shift=0.3)
+    out, H = _gpu_solve(ib, A, block_rows=256, overlap=40, precision="fp32", stop="rel_bound",
+                        lambda_min=0.3, tol=1e-12, max_sweeps=500)
+    assert out.converged
+    assert _rel(H, np.linalg.inv(A)) <= TOL
+    ref = oracle.ibmi_solve(A, oracle.partition(1000, 256, 40), tol=1e-12, stop="rel_bound",
+                            lam_min=0.3)
+    assert _rel(H, ref.h) <= TOL
+
+
+def test_mixed_first_sweep_close_to_fp64(ib):
+    """One mixed sweep differs from the FP64 sweep only by FP32 rounding of D A[:,I]; in the
+    first sweep D is bounded by |H|, so the difference is a small multiple of u_fp32 * kappa."""
+    _say("mixed vs fp64 single sweep p=777")
+    A = workloads.wishart_spd(777, np.random.default_rng(6), shift=0.5)
+    ranges = oracle.partition(777, 200, 24)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-300, fixed_sweeps=2)
+    out, H = _gpu_solve(ib, A, bounds=ranges, precision="fp32", tol=1e-300, fixed_sweeps=2)
+    kappa = np.linalg.cond(A)
+    assert _rel(H, ref.h) < 100 * np.finfo(np.float32).eps * kappa
+
+
+def test_sweep_entry_point_matches_solve(ib):
+    _say("ibmi_sweep vs ibmi_solve p=640")
+    A = workloads.config2_matrix(p=640)
+    for prec in ("fp64", "fp32"):
+        plan = ib.Plan(_dev(A), block_rows=200, overlap=24, precision=prec, fixed_sweeps=3,
+                       tol=1e-300)
+        h_solve = plan.solve().H.clone()
+        H = torch.empty_like(h_solve)
+        ib.ibmi_init_h(plan.handle, H)
+        res = [ib.ibmi_sweep(plan.handle, H, r == 0) for r in range(3)]
+        torch.cuda.synchronize()
+        assert torch.equal(H, h_solve), prec
+        assert res[-1] == pytest.approx(plan.residual(H), rel=1e-12)
+        plan.close()
