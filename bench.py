@@ -49,6 +49,43 @@ def cpu_baseline(A, ranges, n_sets):
                       f"sweep 1 from H = I at p={p} (FP64 NumPy/OpenBLAS), {dt:.1f} s"}
 
 
+def batched_bench(ib, torch, oracle):
+    """256 Wishart matrices (p log-uniform in [128, 2048]), b = 128, overlap 16, tol 1e-8,
+    solved as one batch: cached/autotuned tile shapes, then a timed solve."""
+    import workloads
+    from paper_2502_06377_amd import tuning
+    log("[batched] generating 256 matrices")
+    mats = workloads.config4_batch()
+    dev = []
+    for a in mats:
+        p = a.shape[0]
+        ld = (p + 7) // 8 * 8
+        t = torch.zeros((p, ld), dtype=torch.float64, device="cuda:0")
+        t[:, :p] = torch.from_numpy(a)
+        dev.append(t[:, :p])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = ib.BatchPlan(dev, block_rows=128, overlap=16, tol=1e-8, max_sweeps=500)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    tune = tuning.tuned(batch)
+    log(f"[batched] tuning {tune}")
+    batch.solve()  # warm-up (builds the graph for these buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = batch.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flops = sum(oracle.flops_sweep(a.shape[0], oracle.partition(a.shape[0], 128, 16)) * o.sweeps
+                for a, o in zip(mats, outs))
+    batch.close()
+    return {"matrices": len(mats), "s_per_batch": round(dt, 4), "plan_s": round(plan_s, 4),
+            "solves_per_s": round(len(mats) / dt, 2), "tflops": round(flops / dt / 1e12, 3),
+            "sweeps_max": max(o.sweeps for o in outs),
+            "sweeps_mean": round(sum(o.sweeps for o in outs) / len(outs), 2),
+            "all_converged": all(o.converged for o in outs), "tile_cfg": list(tune["cfg"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,9 +93,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--p", type=int, default=16384)
     ap.add_argument("--full-solve", action="store_true")
+    ap.add_argument("--max-sweeps", type=int, default=3000)
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the batched form on 256 matrices, p log-uniform in [128, 2048]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sets", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -68,6 +110,14 @@ def main():
     import torch
     import workloads
     import paper_2502_06377_amd as ib
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8}), flush=True)
+        return
 
     p, block_rows, overlap, nugget = args.p, 576, 64, 1e-3
     log(f"generating workload p={p}")
@@ -157,18 +207,34 @@ def main():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fplan = ib.Plan(A, block_rows=block_rows, overlap=overlap, precision=prec,
-                            stop="rel_bound", lambda_min=nugget, tol=1e-10, max_sweeps=500)
-            sol = fplan.solve(H)
+                            stop="rel_bound", lambda_min=nugget, tol=1e-10,
+                            max_sweeps=args.max_sweeps)
+
+            def progress(r, res, sv, prec=prec):
+                if r % 50 == 0:
+                    log(f"[{prec}] sweep {r}: ||I-AH||_F = {res:.3e}, bound {sv:.3e}")
+                return False
+
+            sol = fplan.solve(H, progress=progress)
+            if prec == "fp64":
+                H64 = H.clone()
+            else:
+                diff = float(torch.linalg.norm(H - H64) / torch.linalg.norm(H64))
+                out["full_solve"]["fp32_vs_fp64_rel_fro"] = diff
+                del H64
             torch.cuda.synchronize()
             solve_s = time.perf_counter() - t0
             fplan.close()
             out["full_solve"][prec] = {"s_per_solve": round(solve_s, 2), "sweeps": sol.sweeps,
-                                       "converged": sol.converged, "stop_value": sol.stop_value,
-                                       "residual": sol.residual}
+                                       "converged": sol.converged,
+                                       "floor_limited": sol.floor_limited,
+                                       "stop_value": sol.stop_value, "residual": sol.residual}
             log(f"[{prec}] full solve: {sol.sweeps} sweeps, {solve_s:.1f} s, "
                 f"bound {sol.stop_value:.2e}")
     del H, A
     torch.cuda.empty_cache()
+    if args.batched:
+        out["batched_form"] = batched_bench(ib, torch, oracle)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(A_host, ranges, args.cpu_sets)

@@ -86,6 +86,8 @@ typedef struct {
   int32_t floor_limited;   /* 1 if the stagnation guard stopped the loop                   */
   double residual;         /* ||I - A H||_F after the last sweep                           */
   double stop_value;       /* the quantity compared with tol                               */
+  int32_t cancelled;       /* 1 if the progress callback ended the solve early             */
+  int32_t reserved;
 } ibmi_info;
 
 typedef struct ibmi_plan_s* ibmi_plan_t;
@@ -134,6 +136,13 @@ ibmi_status ibmi_plan_blocks(ibmi_plan_t plan, int32_t* n_blocks, int64_t* bound
  * NONFINITE if the residual is NaN/Inf (H then holds the offending iterate). */
 ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* info, double* history);
 
+/* Progress callback of ibmi_solve: called on the calling thread after every sweep with the
+ * number of sweeps done, ||I - A H||_F and the stop value.  A nonzero return ends the solve
+ * after that sweep (status OK, converged = 0, cancelled = 1).  fn = NULL removes it. */
+typedef int32_t (*ibmi_progress_fn)(int32_t sweep, double residual, double stop_value,
+                                    void* user);
+ibmi_status ibmi_set_progress(ibmi_plan_t plan, ibmi_progress_fn fn, void* user);
+
 /* One sweep (sets k = 1..K in order) in the plan's precision form, then ||I - A H||_F written
  * to *residual (host, nullable); synchronises once.  The FP32-update form carries the
  * residual matrix of the previous sweep in the workspace: pass restart = 1 on the first call
@@ -167,6 +176,52 @@ ibmi_status ibmi_kernel_times(ibmi_plan_t plan, double* ms, int64_t* launches, d
 
 /* Release the host-side plan object.  Does not free A or the workspace (caller-owned). */
 ibmi_status ibmi_plan_destroy(ibmi_plan_t plan);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many independent SPD matrices of uneven order solved together.  All
+ * matrices share block_rows, overlap, tol, max_sweeps and the stagnation guard of opts
+ * (init = IDENTITY, stop = FRO, precision = FP64).  Every sweep of every matrix is one
+ * replay of a captured HIP graph: per set index j, one grouped launch of the panel products
+ * of set j of all matrices, one grouped split-K diagonal launch and one grouped
+ * finalisation; then a grouped residual, a per-matrix reduction and an on-device stop test
+ * that marks converged or capped matrices inactive.  Inactive matrices are skipped by every
+ * later kernel, so their H stays at the sweep where they stopped.
+ * --------------------------------------------------------------------------------------- */
+typedef struct ibmi_batch_s* ibmi_batch_t;
+
+/* Workspace bytes for n matrices of orders p[0..n) (host array). 0 if invalid. */
+size_t ibmi_batch_workspace_bytes(int32_t n, const int64_t* p, const ibmi_options* opts);
+
+/* Plan the batch: block factors of every set of every matrix (one launch per stage).
+ *  dA     host array of n device pointers; matrix i is p[i] x p[i] with leading dimension
+ *         lda[i] >= p[i].  Borrowed until ibmi_batch_destroy.
+ *  dWork  device workspace, 256-byte aligned, >= ibmi_batch_workspace_bytes bytes.
+ * NOT_SPD if any diagonal block of any matrix has a bad pivot. */
+ibmi_status ibmi_batch_plan(ibmi_batch_t* out, int32_t n, const int64_t* p,
+                            const double* const* dA, const int64_t* lda, const ibmi_options* opts,
+                            void* dWork, size_t work_bytes, void* stream);
+
+/* Solve all matrices: H_i = I, then graph replays until every matrix has converged, hit
+ * max_sweeps or stopped on the guard.  dH: host array of n device pointers (p[i] x p[i],
+ * leading dimension ldh[i]).  infos: host array of n.  The task tables and the graph are
+ * built on the first call and rebuilt only when the H pointers or the tuning change.
+ * NONFINITE if some residual became NaN/Inf (its info shows which). */
+ibmi_status ibmi_batch_solve(ibmi_batch_t batch, double* const* dH, const int64_t* ldh,
+                             ibmi_info* infos);
+
+/* Tile configurations (0 <= cfg < 10; see the GEMM configuration table in the sources) of
+ * the grouped panel, diagonal and residual launches. */
+ibmi_status ibmi_batch_set_tuning(ibmi_batch_t batch, int32_t panel, int32_t diag,
+                                  int32_t resid);
+ibmi_status ibmi_batch_get_tuning(ibmi_batch_t batch, int32_t* cfg3);
+
+/* Autotuner: times `reps` graph replays (sweeps from H = I) for each candidate set of tile
+ * configurations on these H buffers, keeps the fastest, and returns it (cfg3, host array of
+ * 3) with its time per sweep in ms.  H contents are overwritten. */
+ibmi_status ibmi_batch_autotune(ibmi_batch_t batch, double* const* dH, const int64_t* ldh,
+                                int32_t reps, int32_t* cfg3, double* ms_per_sweep);
+
+ibmi_status ibmi_batch_destroy(ibmi_batch_t batch);
 
 #ifdef __cplusplus
 }

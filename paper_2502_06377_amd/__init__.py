@@ -48,7 +48,12 @@ class IbmiOptions(ctypes.Structure):
 class IbmiInfo(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("failed_block", ctypes.c_int32), ("floor_limited", ctypes.c_int32),
-                ("residual", ctypes.c_double), ("stop_value", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("stop_value", ctypes.c_double),
+                ("cancelled", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_void_p)
 
 
 _vp, _i64, _i32, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
@@ -69,10 +74,26 @@ _SIGS = {
     "ibmi_init_h": (ctypes.c_int, [_vp, _dp, _i64]),
     "ibmi_residual": (ctypes.c_int, [_vp, _dp, _i64, ctypes.POINTER(ctypes.c_double)]),
     "ibmi_set_profiling": (ctypes.c_int, [_vp, _i32]),
+    "ibmi_set_progress": (ctypes.c_int, [_vp, PROGRESS_FN, _vp]),
     "ibmi_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double)]),
     "ibmi_plan_destroy": (ctypes.c_int, [_vp]),
+    "ibmi_batch_workspace_bytes": (ctypes.c_size_t, [_i32, ctypes.POINTER(ctypes.c_int64),
+                                                     ctypes.POINTER(IbmiOptions)]),
+    "ibmi_batch_plan": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(IbmiOptions), _vp, ctypes.c_size_t, _vp]),
+    "ibmi_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(IbmiInfo)]),
+    "ibmi_batch_set_tuning": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "ibmi_batch_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "ibmi_batch_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_int64), _i32,
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "ibmi_batch_destroy": (ctypes.c_int, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -219,6 +240,7 @@ class SolveOutput:
     residual: float
     stop_value: float
     history: list
+    cancelled: bool = False
 
 
 class Plan:
@@ -236,13 +258,22 @@ class Plan:
         self.handle = ibmi_plan(self.opts, A, self.work, stream)
         self.blocks = ibmi_plan_blocks(self.handle)
 
-    def solve(self, H: torch.Tensor | None = None) -> SolveOutput:
+    def solve(self, H: torch.Tensor | None = None, progress=None) -> SolveOutput:
+        """progress(sweep, residual, stop_value) -> truthy to stop early (optional)."""
         if H is None:
             H = torch.empty((self.p, self.p), dtype=torch.float64, device=self.A.device)
         n = self.opts.fixed_sweeps if self.opts.fixed_sweeps > 0 else self.opts.max_sweeps
-        info, hist = ibmi_solve(self.handle, H, n)
+        cb = None
+        if progress is not None:
+            cb = PROGRESS_FN(lambda r, res, sv, _u: 1 if progress(r, res, sv) else 0)
+            _check(_lib.ibmi_set_progress(self.handle, cb, None), "ibmi_set_progress")
+        try:
+            info, hist = ibmi_solve(self.handle, H, n)
+        finally:
+            if cb is not None:
+                _lib.ibmi_set_progress(self.handle, PROGRESS_FN(), None)
         return SolveOutput(H, info.sweeps, bool(info.converged), bool(info.floor_limited),
-                           info.residual, info.stop_value, hist)
+                           info.residual, info.stop_value, hist, bool(info.cancelled))
 
     def residual(self, H: torch.Tensor) -> float:
         return ibmi_residual(self.handle, H)
@@ -266,3 +297,81 @@ def solve(A: torch.Tensor, **kwargs) -> SolveOutput:
         return plan.solve()
     finally:
         plan.close()
+
+
+# ------------------------------------------------------------------ batched form
+
+class BatchPlan:
+    """n independent SPD matrices solved together (grouped launches in one captured graph).
+
+    ``As`` is a list of square float64 device tensors with unit column stride; they are
+    borrowed (kept referenced).  H buffers are allocated with a leading dimension rounded up
+    to a multiple of 8 elements so that the 16-byte load path applies."""
+
+    def __init__(self, As, stream=None, **opt_kwargs):
+        self.As = list(As)
+        self.n = len(self.As)
+        self.p = [int(a.shape[0]) for a in self.As]
+        for a in self.As:
+            if a.dtype != torch.float64 or a.dim() != 2 or a.stride(1) != 1:
+                raise ValueError("each A must be a 2-D float64 tensor with unit column stride")
+        self.opts = make_options(max(self.p), **opt_kwargs)
+        self._p = (ctypes.c_int64 * self.n)(*self.p)
+        nbytes = _lib.ibmi_batch_workspace_bytes(self.n, self._p, ctypes.byref(self.opts))
+        if nbytes == 0:
+            raise IbmiError(IBMI_ERR_INVALID_ARG, "ibmi_batch_workspace_bytes")
+        dev = self.As[0].device
+        self.work = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        ptrs = (ctypes.c_void_p * self.n)(*[_dptr(a) for a in self.As])
+        ldas = (ctypes.c_int64 * self.n)(*[a.stride(0) for a in self.As])
+        # graph capture needs a stream of its own (not the legacy default stream)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        h = _vp()
+        _check(_lib.ibmi_batch_plan(ctypes.byref(h), self.n, self._p, ptrs, ldas,
+                                    ctypes.byref(self.opts), _dptr(self.work), int(nbytes),
+                                    self.stream.cuda_stream), "ibmi_batch_plan")
+        self.handle = h.value
+        self.H = []
+        for p in self.p:
+            ld = (p + 7) // 8 * 8
+            self.H.append(torch.empty((p, ld), dtype=torch.float64, device=dev)[:, :p])
+        self._hp = (ctypes.c_void_p * self.n)(*[h.data_ptr() for h in self.H])
+        self._hld = (ctypes.c_int64 * self.n)(*[h.stride(0) for h in self.H])
+
+    def solve(self):
+        infos = (IbmiInfo * self.n)()
+        self.stream.wait_stream(torch.cuda.current_stream(self.As[0].device))
+        st = _lib.ibmi_batch_solve(self.handle, self._hp, self._hld, infos)
+        out = [SolveOutput(self.H[i], infos[i].sweeps, bool(infos[i].converged),
+                           bool(infos[i].floor_limited), infos[i].residual, infos[i].stop_value, [])
+               for i in range(self.n)]
+        _check(st, "ibmi_batch_solve")
+        return out
+
+    def set_tuning(self, panel: int, diag: int, resid: int) -> None:
+        _check(_lib.ibmi_batch_set_tuning(self.handle, panel, diag, resid), "ibmi_batch_set_tuning")
+
+    def get_tuning(self) -> tuple:
+        c = (ctypes.c_int32 * 3)()
+        _check(_lib.ibmi_batch_get_tuning(self.handle, c), "ibmi_batch_get_tuning")
+        return tuple(c)
+
+    def autotune(self, reps: int = 2):
+        self.stream.wait_stream(torch.cuda.current_stream(self.As[0].device))
+        c = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double(0.0)
+        _check(_lib.ibmi_batch_autotune(self.handle, self._hp, self._hld, reps, c,
+                                        ctypes.byref(ms)), "ibmi_batch_autotune")
+        return tuple(c), ms.value
+
+    def close(self):
+        if getattr(self, "handle", 0):
+            _check(_lib.ibmi_batch_destroy(self.handle), "ibmi_batch_destroy")
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <vector>
 
+#include "host.h"
 #include "kernels.h"
 
 using ibmi::BlockDesc;
@@ -32,9 +33,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
     if ((call) != hipSuccess) return IBMI_ERR_HIP; \
   } while (0)
 
+}  // namespace
+
 // The partition reading documented in ibmi.h (ibmi_partition).
-void default_partition(int64_t p, int64_t b, int64_t ovl, std::vector<int64_t>& s,
-                       std::vector<int64_t>& e) {
+void ibmi::default_partition(int64_t p, int64_t b, int64_t ovl, std::vector<int64_t>& s,
+                             std::vector<int64_t>& e) {
   s.clear();
   e.clear();
   if (p <= b) {
@@ -61,6 +64,9 @@ void default_partition(int64_t p, int64_t b, int64_t ovl, std::vector<int64_t>& 
     e.push_back(std::min(p, ce[k] + hr));
   }
 }
+
+namespace {
+using ibmi::default_partition;
 
 // Validated sets of a plan (partitioner or explicit bounds).
 ibmi_status make_sets(const ibmi_options* o, std::vector<int64_t>& s, std::vector<int64_t>& e) {
@@ -138,6 +144,18 @@ Tuning tuning_for(int64_t p) {
   return t;
 }
 
+}  // namespace
+
+// Default tile configurations of the batched form's grouped launches (small matrices: small
+// tiles, many resident waves); IBMI_CFG_* environment overrides apply as for single plans.
+void ibmi::batch_tuning(GemmCfg* panel, GemmCfg* diag, GemmCfg* resid) {
+  *panel = env_cfg("IBMI_CFG_PANEL", ibmi::GEMM_64x64_K16);
+  *diag = env_cfg("IBMI_CFG_DIAG", ibmi::GEMM_64x64_K16);
+  *resid = env_cfg("IBMI_CFG_RESID", ibmi::GEMM_64x64_K16);
+}
+
+namespace {
+
 int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
   if (c <= 0) return 1;
   if (forced > 0) return (int)std::min<int64_t>(forced, std::max<int64_t>(1, c / 64));
@@ -167,7 +185,7 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
   int64_t fac = 0, wt = 0;
   for (int k = 0; k < K; ++k) {
     const int64_t b = e[k] - s[k], c = p - b;
-    BlockDesc d;
+    BlockDesc d{};
     d.s = s[k];
     d.b = b;
     d.l_off = fac;
@@ -267,6 +285,8 @@ struct Timer {
 
 struct ibmi_plan_s {
   ibmi_options o;
+  ibmi_progress_fn progress = nullptr;
+  void* progress_user = nullptr;
   bool profiling = false;
   Timer timers[3];
   std::vector<int64_t> s, e;
@@ -623,7 +643,7 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
   if (rc != IBMI_OK) return rc;
   if (!info) return IBMI_ERR_INVALID_ARG;
   const ibmi_options& o = plan->o;
-  *info = ibmi_info{0, 0, -1, 0, 0.0, 0.0};
+  *info = ibmi_info{0, 0, -1, 0, 0.0, 0.0, 0, 0};
   rc = ibmi_init_h(plan, dH, ldh);
   if (rc != IBMI_OK) return rc;
   const int limit = o.fixed_sweeps > 0 ? o.fixed_sweeps : o.max_sweeps;
@@ -641,6 +661,11 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
     if (history) history[info->sweeps - 1] = rho;
     const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
     info->stop_value = sv;
+    if (plan->progress && plan->progress(info->sweeps, rho, sv, plan->progress_user) != 0) {
+      info->cancelled = 1;
+      info->converged = o.fixed_sweeps > 0 ? 0 : (sv < o.tol);
+      break;
+    }
     if (o.fixed_sweeps > 0) {
       if (info->sweeps >= limit) {
         info->converged = sv < o.tol;
@@ -660,6 +685,13 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
       break;
     }
   }
+  return IBMI_OK;
+}
+
+ibmi_status ibmi_set_progress(ibmi_plan_t plan, ibmi_progress_fn fn, void* user) {
+  if (!plan) return IBMI_ERR_INVALID_ARG;
+  plan->progress = fn;
+  plan->progress_user = user;
   return IBMI_OK;
 }
 

@@ -29,27 +29,76 @@ struct BlockDesc {
   int64_t l_off;      // b*b: Cholesky factor, lower = L, strict upper = L^T
   int64_t linv_off;   // b*b: L^{-1} (lower triangle, zeros above)
   int64_t ainv_off;   // b*b: A_I^{-1}, bitwise symmetric
+  const double* a;    // the set's matrix (batched plans; single plans pass A to the kernel)
+  int64_t lda;
+};
+
+// Epilogue kinds of the MFMA GEMM and their arguments.
+enum {
+  EPI_STORE = 0,        // out[m][n] = C
+  EPI_PANEL = 1,        // H[s+m][g(n)] = H[g(n)][s+m] = -C
+  EPI_PARTIAL = 2,      // out[z][m][n] = C over K chunk z
+  EPI_RESID = 3,        // red[slot] = sum over the tile of (delta_mn - C)^2
+  EPI_RESID_STORE = 4,  // out[m][n] = delta_mn - C and red[slot] = sum of its squares
+  EPI_SUBFROM = 5,      // out[m][n] = src[(s+m)][n] - C
+  EPI_CORR = 6          // correction of H[I^c,I] and D (FP32-update form)
+};
+
+struct EpiArgs {
+  double* out = nullptr;   // primary output
+  int64_t ldo = 0;
+  int64_t s = 0;           // first row of I
+  IdxMap g;                // column map of I^c
+  double* red = nullptr;   // per-tile partial sums (residual epilogues)
+  const double* src = nullptr;  // subtrahend rows (EPI_SUBFROM)
+  int64_t lds = 0;
+  double* H = nullptr;     // EPI_CORR targets
+  int64_t ldh = 0;
+  float* D = nullptr;
+  int64_t ldd = 0;
+  int64_t ncut = INT64_MAX;  // column tiles starting at or after ncut stop K at klim
+  int64_t klim = 0;
+};
+
+// One product of a grouped (batched) launch.
+struct GemmTask {
+  Opnd X, Y;
+  int64_t M, N, K, kchunk;
+  int32_t mtc, ntc, splits, mat;
+  EpiArgs ea;
+};
+
+// Elementwise b x b task: diagonal finalisation (x = A_I^{-1}, part = split-K partials,
+// out = H at rows/cols [s, s+b)) or symmetrisation (out = (x + x^T)/2, b x b).
+struct FinTask {
+  const double* x;
+  const double* part;
+  double* out;
+  int64_t b, ldo, s;
+  int32_t splits, mat;
+};
+
+// Per-matrix state of a batched solve.
+struct BatchState {
+  int32_t sweeps, converged, floor_limited, pad;
+  double residual;
+  double hist[3];
 };
 
 // Tile configurations of the MFMA GEMM: workgroup tile, waves, and the number of
 // independent 16x16 accumulation chains each wave carries.
 enum GemmCfg {
-  GEMM_64x64 = 0,     // 2x2 waves of 32x32 ( 4 chains), BK 32
-  GEMM_128x128 = 1,   // 2x2 waves of 64x64 (16 chains), BK 32
-  GEMM_96x128 = 2,    // 2x2 waves of 48x64 (12 chains), BK 32
-  GEMM_128x64 = 3,    // 2x2 waves of 64x32 ( 8 chains), BK 32
-  GEMM_192x64 = 4,    // 2x2 waves of 96x32 (12 chains), BK 32
-  GEMM_64x64_W1 = 5,  // 1 wave of 64x64    (16 chains), BK 16
-  GEMM_32x64_W1 = 6,  // 1 wave of 32x64    ( 8 chains), BK 16
-  GEMM_64x64_K16 = 7,    // 2x2 waves of 32x32 ( 4 chains), BK 16
-  GEMM_128x64_K16 = 8,   // 2x2 waves of 64x32 ( 8 chains), BK 16
-  GEMM_64x128_K16 = 9,   // 2x2 waves of 32x64 ( 8 chains), BK 16
-  GEMM_128x128_W8 = 10,  // 2x4 waves of 64x32 ( 8 chains), BK 16
-  GEMM_128x128_W16 = 11, // 4x4 waves of 32x32 ( 4 chains), BK 16
-  GEMM_96x64_K16 = 12,   // 2x2 waves of 48x32 ( 6 chains), BK 16
-  GEMM_192x128_W8 = 13,  // 2x4 waves of 96x32 (12 chains), BK 16
-  GEMM_64x64_W2 = 14,    // 2x1 waves of 32x64 ( 8 chains), BK 32
-  GEMM_CFG_COUNT = 15
+  GEMM_64x64 = 0,       // 2x2 waves of 32x32 ( 4 chains), BK 32
+  GEMM_64x64_K16 = 1,   // 2x2 waves of 32x32 ( 4 chains), BK 16
+  GEMM_128x128_W8 = 2,  // 2x4 waves of 64x32 ( 8 chains), BK 16
+  GEMM_96x128_W8 = 3,   // 2x4 waves of 48x32 ( 6 chains), BK 32
+  GEMM_96x64_K16 = 4,   // 2x2 waves of 48x32 ( 6 chains), BK 16
+  GEMM_64x128_K16 = 5,  // 2x2 waves of 32x64 ( 8 chains), BK 16
+  GEMM_64x64_W1 = 6,    // 1 wave of 64x64    (16 chains), BK 16
+  GEMM_32x64_W1 = 7,    // 1 wave of 32x64    ( 8 chains), BK 16
+  GEMM_64x64_W2 = 8,    // 2x1 waves of 32x64 ( 8 chains), BK 32
+  GEMM_96x128 = 9,      // 2x2 waves of 48x64 (12 chains), BK 32
+  GEMM_CFG_COUNT = 10
 };
 struct GemmDims {
   int bm, bn;
@@ -90,7 +139,25 @@ hipError_t corr_diag(const double* rkt, int64_t ldr, int64_t s, const double* pa
 hipError_t corr_apply(const double* x, int64_t b, double* H, int64_t ldh, float* D, int64_t ldd,
                       int64_t s, hipStream_t st);
 
+// Grouped launch of tasks[0..ntasks) (tile prefix sums in tile_off, total_tiles workgroups);
+// tasks of matrices with active[mat] == 0 are skipped when active is non-null.
+hipError_t gemm_grouped(GemmCfg cfg, int epi, const GemmTask* tasks, const int* tile_off,
+                        int ntasks, int total_tiles, const int* active, bool vec, hipStream_t st);
+// Whether the fast 16-byte load path is valid for both operands of a task.
+bool gemm_vec_ok(const GemmTask& t);
+hipError_t symmetrize_grouped(const FinTask* tasks, int ntasks, hipStream_t st);
+hipError_t diag_finalize_grouped(const FinTask* tasks, int ntasks, const int* active,
+                                 hipStream_t st);
+// After a batched sweep: per-matrix residual from its tile partial sums (fixed order), then
+// the stop test; active[i] = 0 once matrix i converged or reached max_sweeps; active[n] =
+// number still active.
+hipError_t batch_check(const double* red, const int* red_off, int n, int* active,
+                       BatchState* state, double tol, int max_sweeps, int guard,
+                       hipStream_t st);
+hipError_t batch_reset(int* active, BatchState* state, int n, hipStream_t st);
+
 // Block factors (one launch for all sets of a plan).
+// A may be null: each set then reads its own matrix from its descriptor (batched plans).
 hipError_t chol_factor(const BlockDesc* d_desc, int n_blocks, int64_t b_max, const double* A,
                        int64_t lda, double* fac, int* d_status, hipStream_t st);
 hipError_t chol_linv(const BlockDesc* d_desc, int n_blocks, int64_t b_max, double* fac,

@@ -1,463 +1,16 @@
-// gfx950 (CDNA4) kernels of the IBMI library.
-//
-// The hot path of a sweep is three dense FP64 contractions per set I (eq. (IBMI)):
-//   panel  V = W H[I^c,I^c]             (b x c x c, the dominant 2 b c^2 term)
-//   diag   G = W H[I^c,I]  -> H[I,I]    (b x b x c, the 2 b^2 c term, split over K)
-//   resid  ||I - A H||_F                (p x p x p, once per sweep)
-// All three run on one FP64 MFMA GEMM template (v_mfma_f64_16x16x4f64) that reads both
-// operands as "row k, column x" through index maps, so the two-segment complement
-// I^c = [0,s) u [e,p) is addressed in place and never gathered into a copy.  Block factors
-// (Cholesky, L^{-1}, A_I^{-1}) run once per plan.
+// gfx950 (CDNA4) kernels of the IBMI library other than the GEMMs: block factors (Cholesky,
+// L^{-1}; once per plan), diagonal finalisation, initialisation, reductions, the FP32-update
+// helpers and the batched-form bookkeeping.  The GEMM templates live in gemm.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
+#include "gemm.h"
 #include "kernels.h"
 
 namespace ibmi {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-enum {
-  EPI_STORE = 0,        // out[m][n] = C
-  EPI_PANEL = 1,        // H[s+m][g(n)] = H[g(n)][s+m] = -C
-  EPI_PARTIAL = 2,      // out[z][m][n] = C over K chunk z
-  EPI_RESID = 3,        // red[tile] = sum (delta_mn - C)^2
-  EPI_RESID_STORE = 4,  // out[m][n] = delta_mn - C and red[tile] = sum of its squares
-  EPI_SUBFROM = 5,      // out[m][n] = src[(s+m)][n] - C
-  EPI_CORR = 6          // correction of H[I^c,I] and D (see below)
-};
-
-struct EpiArgs {
-  double* out = nullptr;   // primary output
-  int64_t ldo = 0;
-  int64_t s = 0;           // first row of I
-  IdxMap g;                // column map of I^c
-  double* red = nullptr;   // per-tile partial sums (residual epilogues)
-  const double* src = nullptr;  // subtrahend rows (EPI_SUBFROM)
-  int64_t lds = 0;
-  double* H = nullptr;     // EPI_CORR targets
-  int64_t ldh = 0;
-  float* D = nullptr;
-  int64_t ldd = 0;
-  int64_t ncut = INT64_MAX;  // column tiles starting at or after ncut stop K at klim
-  int64_t klim = 0;
-};
-
-// Integer min/max written out: the generic device min/max templates route 64-bit integers
-// through floating point.
-__device__ __forceinline__ int64_t mn64(int64_t a, int64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int64_t mx64(int64_t a, int64_t b) { return a > b ? a : b; }
-__device__ __forceinline__ int mn32(int a, int b) { return a < b ? a : b; }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// MFMA 16x16x4 for the two element types, with their result layouts as measured on gfx950:
-// register r of lane l holds row 4r + l/16 (FP64) or row 4(l/16) + r (FP32), column l%16.
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef v4d acc_t;
-  static __device__ __forceinline__ v4d op(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
-};
-template <> struct Mfma<float> {
-  typedef v4f acc_t;
-  static __device__ __forceinline__ v4f op(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
-};
-
-// ---------------------------------------------------------------------------------------
-// MFMA GEMM: C[m][n] = sum_k X(k, m) Y(k, n), operands of type T, C accumulated in T.
-//
-// Workgroup tile BM x BN, K staged BK at a time through LDS (double buffered: global loads
-// for stage t+1 are in flight while stage t feeds the matrix cores).  WM x WN waves, each
-// owning a (BM/WM) x (BN/WN) block of 16x16 MFMA tiles; every tile is an independent
-// accumulation chain, and a wave needs about 8 of them in flight to keep the FP64 matrix
-// pipe busy (a measured property of gfx950: 4 chains per wave reach ~60% of peak).
-// Operand tiles sit in LDS as they sit in memory ([k][x], x contiguous), which is also the
-// order the MFMA fragments are read in: lane l takes X(k0 + l/16, x0 + l%16), so each
-// ds_read touches 4 rows of 16 consecutive elements.
-//
-// Tile order: workgroup ids are dealt to the 8 XCDs round-robin, so id -> (xcd = id & 7,
-// slot = id >> 3) and each XCD walks its own contiguous range of tiles; within that range
-// tiles go in groups of `gm` M-tiles per N column so the workgroups resident on one XCD share
-// operand panels in that XCD's L2.
-// ---------------------------------------------------------------------------------------
-// VEC-wide loads need every thread to own a multiple of VEC elements of each operand tile.
-template <int XE, int YE, int VEC>
-struct VecWidth {
-  static constexpr int value =
-      (XE % VEC == 0 && YE % VEC == 0) ? VEC : ((XE % 2 == 0 && YE % 2 == 0) ? 2 : 1);
-};
-
-template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ>
-__global__ void __launch_bounds__(64 * WM * WN)
-gemm_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int64_t kchunk, int mtc, int ntc,
-            int per_xcd, int gm, EpiArgs ea) {
-  typedef Mfma<T> MF;
-  typedef typename MF::acc_t acc_t;
-  constexpr int NT = 64 * WM * WN;
-  constexpr int WTM = BM / WM, WTN = BN / WN;
-  constexpr int TM = WTM / 16, TN = WTN / 16;
-  constexpr int XE = BK * BM / NT, YE = BK * BN / NT;
-  constexpr int VEC = VREQ == 1 ? 1 : VecWidth<XE, YE, VREQ>::value;
-  typedef T vec_t __attribute__((ext_vector_type(VEC)));
-  constexpr int XV = XE / VEC, YV = YE / VEC;
-  static_assert(XE * NT == BK * BM && YE * NT == BK * BN, "tile not divisible by threads");
-  static_assert(XV * VEC == XE && YV * VEC == YE && BM % VEC == 0 && BN % VEC == 0, "bad VEC");
-  static_assert(TM * 16 == WTM && TN * 16 == WTN && BK % 4 == 0, "bad wave tile");
-
-  __shared__ __attribute__((aligned(16))) T Xs[2][BK][BM];
-  __shared__ __attribute__((aligned(16))) T Ys[2][BK][BN];
-  __shared__ double red_s[NT / 64];
-
-  const int tid = threadIdx.x;
-  const int bx = blockIdx.x;
-  const int q = (bx & 7) * per_xcd + (bx >> 3);
-  const int tiles = mtc * ntc;
-  if (q >= tiles) return;
-  int mt, nt;
-  {
-    const int width = gm * ntc;
-    const int grp = q / width;
-    const int first_m = grp * gm;
-    const int gsz = mn32(mtc - first_m, gm);
-    const int rem = q - grp * width;
-    mt = first_m + rem % gsz;
-    nt = rem / gsz;
-  }
-  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
-  const int64_t ke = mn64(n0 >= ea.ncut ? mn64(K, ea.klim) : K, kb + kchunk);
-  const int nk = ke > kb ? (int)((ke - kb + BK - 1) / BK) : 0;
-
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % WM, wn = wave / WM;
-  const int lr = lane & 15, lk = lane >> 4;
-  const T* __restrict__ xp = (const T*)X.ptr;
-  const T* __restrict__ yp = (const T*)Y.ptr;
-
-  // Interior tiles (all columns in range) take a branch-free path of VEC-wide loads: per stage
-  // the operand's row base is a wave-uniform pointer and each thread adds a fixed 32-bit
-  // offset (its row within the stage times ld, plus its mapped column), bumped by skip*ld
-  // for rows past the map's cut.  Edge tiles and a ragged last K stage take the
-  // bounds-checked scalar path.  The choice is uniform over the workgroup.
-  const bool interior = VEC > 1 && m0 + BM <= M && n0 + BN <= N;
-  int xkk[XV], xoff[XV], ykk[YV], yoff[YV];
-#pragma unroll
-  for (int v = 0; v < XV; ++v) {
-    const int idx = (tid + v * NT) * VEC;
-    xkk[v] = idx / BM;
-    xoff[v] = interior ? xkk[v] * (int)X.ld + (int)X.c(m0 + idx % BM) : 0;
-  }
-#pragma unroll
-  for (int v = 0; v < YV; ++v) {
-    const int idx = (tid + v * NT) * VEC;
-    ykk[v] = idx / BN;
-    yoff[v] = interior ? ykk[v] * (int)Y.ld + (int)Y.c(n0 + idx % BN) : 0;
-  }
-  const int xskipld = (int)(X.r.skip * X.ld), yskipld = (int)(Y.r.skip * Y.ld);
-
-  T xr[XE], yr[YE];
-  auto gload = [&](int kt) {
-    const int64_t k0 = kb + (int64_t)kt * BK;
-    if (interior && k0 + BK <= ke) {
-      const T* xb = xp + (X.r.base + k0) * X.ld;
-      const T* yb = yp + (Y.r.base + k0) * Y.ld;
-      const int xcut = (int)mn64(mx64(X.r.cut - k0, -1), BK + 1);
-      const int ycut = (int)mn64(mx64(Y.r.cut - k0, -1), BK + 1);
-#pragma unroll
-      for (int v = 0; v < XV; ++v) {
-        const int off = xoff[v] + (xkk[v] >= xcut ? xskipld : 0);
-        const vec_t t = *(const vec_t*)(xb + off);
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) xr[v * VEC + u] = t[u];
-      }
-#pragma unroll
-      for (int v = 0; v < YV; ++v) {
-        const int off = yoff[v] + (ykk[v] >= ycut ? yskipld : 0);
-        const vec_t t = *(const vec_t*)(yb + off);
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) yr[v * VEC + u] = t[u];
-      }
-      return;
-    }
-#pragma unroll
-    for (int e = 0; e < XE; ++e) {
-      const int idx = (tid + (e / VEC) * NT) * VEC + e % VEC;
-      const int64_t gk = k0 + idx / BM, gx = m0 + idx % BM;
-      xr[e] = (gk < ke && gx < M) ? xp[X.r(gk) * X.ld + X.c(gx)] : T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < YE; ++e) {
-      const int idx = (tid + (e / VEC) * NT) * VEC + e % VEC;
-      const int64_t gk = k0 + idx / BN, gx = n0 + idx % BN;
-      yr[e] = (gk < ke && gx < N) ? yp[Y.r(gk) * Y.ld + Y.c(gx)] : T(0);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int v = 0; v < XV; ++v) {
-      const int idx = (tid + v * NT) * VEC;
-      vec_t t;
-#pragma unroll
-      for (int u = 0; u < VEC; ++u) t[u] = xr[v * VEC + u];
-      *(vec_t*)&Xs[buf][idx / BM][idx % BM] = t;
-    }
-#pragma unroll
-    for (int v = 0; v < YV; ++v) {
-      const int idx = (tid + v * NT) * VEC;
-      vec_t t;
-#pragma unroll
-      for (int u = 0; u < VEC; ++u) t[u] = yr[v * VEC + u];
-      *(vec_t*)&Ys[buf][idx / BN][idx % BN] = t;
-    }
-  };
-
-  acc_t acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
-  if (nk > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = Xs[cur][kk + lk][wm * WTM + 16 * i + lr];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Ys[cur][kk + lk][wn * WTN + 16 * j + lr];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
-    }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
-  }
-
-  double ss = 0.0;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm * WTM + 16 * i + MF::row(r, lk);
-        const int64_t n = n0 + wn * WTN + 16 * j + lr;
-        const double v = (double)acc[i][j][r];
-        if (m >= M || n >= N) continue;
-        if constexpr (EPI == EPI_STORE) {
-          ea.out[m * ea.ldo + n] = v;
-        } else if constexpr (EPI == EPI_PANEL) {
-          const int64_t gn = ea.g(n);
-          ea.out[(ea.s + m) * ea.ldo + gn] = -v;
-          ea.out[gn * ea.ldo + ea.s + m] = -v;
-        } else if constexpr (EPI == EPI_PARTIAL) {
-          ea.out[(int64_t)blockIdx.y * M * N + m * N + n] = v;
-        } else if constexpr (EPI == EPI_RESID) {
-          const double d = (m == n ? 1.0 : 0.0) - v;
-          ss += d * d;
-        } else if constexpr (EPI == EPI_RESID_STORE) {
-          const double d = (m == n ? 1.0 : 0.0) - v;
-          ea.out[m * ea.ldo + n] = d;
-          ss += d * d;
-        } else if constexpr (EPI == EPI_SUBFROM) {
-          ea.out[m * ea.ldo + n] = ea.src[(ea.s + m) * ea.lds + n] - v;
-        } else {
-          // EPI_CORR: C = Delta[m][n] (m over I^c, n over I).  Store Delta, then add it to
-          // H[g(m)][s+n] and mirror the new value to H[s+n][g(m)]; the same for the FP32
-          // change D, so H and D stay bitwise symmetric.
-          ea.out[m * ea.ldo + n] = v;
-          const int64_t gm_ = ea.g(m), cn = ea.s + n;
-          const double hn = ea.H[gm_ * ea.ldh + cn] + v;
-          ea.H[gm_ * ea.ldh + cn] = hn;
-          ea.H[cn * ea.ldh + gm_] = hn;
-          const float dn = ea.D[gm_ * ea.ldd + cn] + (float)v;
-          ea.D[gm_ * ea.ldd + cn] = dn;
-          ea.D[cn * ea.ldd + gm_] = dn;
-        }
-      }
-  if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_STORE) {
-    ss = wave_sum(ss);
-    if (lane == 0) red_s[wave] = ss;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < NT / 64; ++w) t += red_s[w];
-      ea.red[q] = t;
-    }
-  }
-}
-
-// (BM, BN, BK, WM, WN) of every configuration, in GemmCfg order.
-#define IBMI_GEMM_CONFIGS(X_)                                                                  \
-  X_(GEMM_64x64, 64, 64, 32, 2, 2)                                                             \
-  X_(GEMM_128x128, 128, 128, 32, 2, 2)                                                         \
-  X_(GEMM_96x128, 96, 128, 32, 2, 2)                                                           \
-  X_(GEMM_128x64, 128, 64, 32, 2, 2)                                                           \
-  X_(GEMM_192x64, 192, 64, 32, 2, 2)                                                           \
-  X_(GEMM_64x64_W1, 64, 64, 16, 1, 1)                                                          \
-  X_(GEMM_32x64_W1, 32, 64, 16, 1, 1)                                                          \
-  X_(GEMM_64x64_K16, 64, 64, 16, 2, 2)                                                         \
-  X_(GEMM_128x64_K16, 128, 64, 16, 2, 2)                                                       \
-  X_(GEMM_64x128_K16, 64, 128, 16, 2, 2)                                                       \
-  X_(GEMM_128x128_W8, 128, 128, 16, 2, 4)                                                      \
-  X_(GEMM_128x128_W16, 128, 128, 16, 4, 4)                                                     \
-  X_(GEMM_96x64_K16, 96, 64, 16, 2, 2)                                                         \
-  X_(GEMM_192x128_W8, 192, 128, 16, 2, 4)                                                      \
-  X_(GEMM_64x64_W2, 64, 64, 32, 2, 1)
-
-GemmDims gemm_dims(GemmCfg c) {
-  switch (c) {
-#define IBMI_DIMS(NAME, BM_, BN_, BK_, WM_, WN_) \
-  case NAME:                                     \
-    return {BM_, BN_};
-    IBMI_GEMM_CONFIGS(IBMI_DIMS)
-#undef IBMI_DIMS
-    default: return {64, 64};
-  }
-}
-
-// True when every VEC-wide run of columns x, x+1, .. (x a multiple of VEC) of the operand is
-// contiguous and 16-byte aligned in memory.
-// The fast path also needs every per-thread offset (row-in-stage * ld + column + skip * ld)
-// to fit in 32 bits.
-template <typename T>
-static bool vec_ok(const Opnd& o, int vec, int64_t ncols) {
-  auto m = [vec](int64_t v) { return v % vec == 0; };
-  const int64_t span = 64 * o.ld + o.c(ncols > 0 ? ncols - 1 : 0) + o.r.skip * o.ld;
-  return ((uintptr_t)o.ptr % 16) == 0 && m(o.ld) && m(o.c.base) && m(o.c.skip) &&
-         (o.c.cut == INT64_MAX || m(o.c.cut)) && span < INT32_MAX;
-}
-
-template <typename T, int EPI>
-static hipError_t launch_gemm(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
-                              int splits, EpiArgs ea, hipStream_t st, int64_t* n_tiles) {
-  constexpr int VMAX = 16 / sizeof(T);
-  const bool vec = vec_ok<T>(X, VMAX, M) && vec_ok<T>(Y, VMAX, N);
-  const GemmDims d = gemm_dims(cfg);
-  const int mtc = (int)((M + d.bm - 1) / d.bm), ntc = (int)((N + d.bn - 1) / d.bn);
-  const int tiles = mtc * ntc;
-  if (n_tiles) *n_tiles = tiles;
-  if (tiles == 0) return hipSuccess;
-  const int per_xcd = (tiles + 7) / 8;
-  const int gm = EPI == EPI_RESID ? 8 : mtc;
-  const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : (K > 0 ? K : 1);
-  const dim3 grid(8 * per_xcd, splits > 1 ? splits : 1);
-#define IBMI_LAUNCH(BM_, BN_, BK_, WM_, WN_)                                                   \
-  do {                                                                                         \
-    if (vec)                                                                                   \
-      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, VMAX>), grid,           \
-                         dim3(64 * WM_ * WN_), 0, st, X, Y, M, N, K, kchunk, mtc, ntc, per_xcd, \
-                         gm, ea);                                                              \
-    else                                                                                       \
-      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, 1>), grid,              \
-                         dim3(64 * WM_ * WN_), 0, st, X, Y, M, N, K, kchunk, mtc, ntc, per_xcd, \
-                         gm, ea);                                                              \
-  } while (0)
-  switch (cfg) {
-#define IBMI_CASE(NAME, BM_, BN_, BK_, WM_, WN_) \
-  case NAME:                                     \
-    IBMI_LAUNCH(BM_, BN_, BK_, WM_, WN_);        \
-    break;
-    IBMI_GEMM_CONFIGS(IBMI_CASE)
-#undef IBMI_CASE
-    default: return hipErrorInvalidValue;
-  }
-#undef IBMI_LAUNCH
-  return hipGetLastError();
-}
-
-hipError_t gemm_store(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* out,
-                      int64_t ldo, hipStream_t st) {
-  EpiArgs ea;
-  ea.out = out;
-  ea.ldo = ldo;
-  return launch_gemm<double, EPI_STORE>(cfg, X, Y, M, N, K, 1, ea, st, nullptr);
-}
-
-hipError_t gemm_panel(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* H,
-                      int64_t ldh, int64_t s, IdxMap g, hipStream_t st) {
-  EpiArgs ea;
-  ea.out = H;
-  ea.ldo = ldh;
-  ea.s = s;
-  ea.g = g;
-  return launch_gemm<double, EPI_PANEL>(cfg, X, Y, M, N, K, 1, ea, st, nullptr);
-}
-
-hipError_t gemm_partial(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int splits,
-                        double* out, hipStream_t st) {
-  EpiArgs ea;
-  ea.out = out;
-  return launch_gemm<double, EPI_PARTIAL>(cfg, X, Y, M, N, K, splits, ea, st, nullptr);
-}
-
-int64_t gemm_tiles(GemmCfg cfg, int64_t M, int64_t N) {
-  const GemmDims d = gemm_dims(cfg);
-  return ((M + d.bm - 1) / d.bm) * ((N + d.bn - 1) / d.bn);
-}
-
-hipError_t gemm_resid(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* red,
-                      int64_t* n_red, double* out, int64_t ldo, hipStream_t st) {
-  EpiArgs ea;
-  ea.red = red;
-  if (out) {
-    ea.out = out;
-    ea.ldo = ldo;
-    return launch_gemm<double, EPI_RESID_STORE>(cfg, X, Y, M, N, K, 1, ea, st, n_red);
-  }
-  return launch_gemm<double, EPI_RESID>(cfg, X, Y, M, N, K, 1, ea, st, n_red);
-}
-
-hipError_t gemm_f32_subfrom(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
-                            int64_t ncut, int64_t klim, const double* src, int64_t lds,
-                            int64_t s, double* out, int64_t ldo, hipStream_t st) {
-  EpiArgs ea;
-  ea.out = out;
-  ea.ldo = ldo;
-  ea.src = src;
-  ea.lds = lds;
-  ea.s = s;
-  ea.ncut = ncut;
-  ea.klim = klim;
-  return launch_gemm<float, EPI_SUBFROM>(cfg, X, Y, M, N, K, 1, ea, st, nullptr);
-}
-
-hipError_t gemm_corr(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* delta,
-                     int64_t ld_delta, double* H, int64_t ldh, float* D, int64_t ldd, int64_t s,
-                     IdxMap g, hipStream_t st) {
-  EpiArgs ea;
-  ea.out = delta;
-  ea.ldo = ld_delta;
-  ea.H = H;
-  ea.ldh = ldh;
-  ea.D = D;
-  ea.ldd = ldd;
-  ea.s = s;
-  ea.g = g;
-  return launch_gemm<double, EPI_CORR>(cfg, X, Y, M, N, K, 1, ea, st, nullptr);
-}
-
 // ---------------------------------------------------------------------------------------
 // Cholesky factor of every diagonal block, one workgroup (16 waves) per set.
 // Right-looking, panels of NB columns held in LDS (row stride NB+1 to spread banks):
@@ -477,6 +30,10 @@ chol_factor_kernel(const BlockDesc* desc, const double* A, int64_t lda, double* 
   const int b = (int)bd.b;
   const int64_t s = bd.s;
   double* L = fac + bd.l_off;
+  if (!A) {
+    A = bd.a;
+    lda = bd.lda;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = CH_THREADS / 64;
 
@@ -593,10 +150,18 @@ __global__ void __launch_bounds__(64) chol_linv_kernel(const BlockDesc* desc, do
 
 hipError_t chol_factor(const BlockDesc* d_desc, int n_blocks, int64_t b_max, const double* A,
                        int64_t lda, double* fac, int* d_status, hipStream_t st) {
+  // The dynamic-LDS limit is a per-kernel attribute shared by every plan in the process, so it
+  // is raised once, to what the largest allowed set (1024 rows) needs, and never lowered:
+  // plans built concurrently on other threads cannot shrink it under each other.
+  static std::once_flag once;
+  static hipError_t attr = hipSuccess;
+  std::call_once(once, [] {
+    attr = hipFuncSetAttribute((const void*)chol_factor_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(1024 * (CH_NB + 1) * sizeof(double)));
+  });
+  if (attr != hipSuccess) return attr;
   const size_t lds = (size_t)b_max * (CH_NB + 1) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)chol_factor_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(chol_factor_kernel, dim3(n_blocks), dim3(CH_THREADS), lds, st, d_desc, A,
                      lda, fac, d_status);
   return hipGetLastError();
@@ -801,6 +366,129 @@ hipError_t corr_apply(const double* x, int64_t b, double* H, int64_t ldh, float*
   const int64_t n = b * b;
   const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(corr_apply_kernel, dim3(grid), dim3(256), 0, st, x, b, H, ldh, D, ldd, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched-form helpers: one workgroup per task (b <= 1024), tasks of inactive matrices skip.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) symmetrize_grouped_kernel(const FinTask* tasks) {
+  const FinTask t = tasks[blockIdx.x];
+  const int64_t n = t.b * t.b;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t i = e / t.b, j = e % t.b;
+    t.out[e] = 0.5 * (t.x[e] + t.x[j * t.b + i]);
+  }
+}
+
+hipError_t symmetrize_grouped(const FinTask* tasks, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_grouped_kernel, dim3(ntasks), dim3(256), 0, st, tasks);
+  return hipGetLastError();
+}
+
+// H[s+i][s+j] = x[i][j] - (G + G^T)/2 with G the fixed-order sum of `splits` partials.
+__global__ void __launch_bounds__(256) diag_finalize_grouped_kernel(const FinTask* tasks,
+                                                                    const int* active) {
+  const FinTask t = tasks[blockIdx.x];
+  if (active && !active[t.mat]) return;
+  const int64_t b = t.b, n = b * b;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t i = e / b, j = e % b;
+    double gij = 0.0, gji = 0.0;
+    for (int z = 0; z < t.splits; ++z) {
+      gij += t.part[z * n + i * b + j];
+      gji += t.part[z * n + j * b + i];
+    }
+    t.out[(t.s + i) * t.ldo + t.s + j] = t.x[e] - 0.5 * (gij + gji);
+  }
+}
+
+hipError_t diag_finalize_grouped(const FinTask* tasks, int ntasks, const int* active,
+                                 hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(diag_finalize_grouped_kernel, dim3(ntasks), dim3(256), 0, st, tasks,
+                     active);
+  return hipGetLastError();
+}
+
+// One workgroup per matrix sums its residual partials in a fixed order and applies the stop
+// test; the last workgroup to finish (atomic ticket) counts the matrices still active.
+__global__ void __launch_bounds__(256) batch_check_kernel(const double* red, const int* red_off,
+                                                          int n, int* active, BatchState* state,
+                                                          double tol, int max_sweeps, int guard,
+                                                          int* ticket) {
+  __shared__ double ws[4];
+  __shared__ int last;
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t t = red_off[i] + threadIdx.x; t < red_off[i + 1]; t += blockDim.x) acc += red[t];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (active[i]) {
+      BatchState s = state[i];
+      const double rho = sqrt(ws[0] + ws[1] + ws[2] + ws[3]);
+      s.sweeps += 1;
+      s.residual = rho;
+      bool stop = false;
+      if (!(rho < INFINITY)) stop = true;           // NaN or Inf: stop, host reports it
+      else if (rho < tol) {
+        s.converged = 1;
+        stop = true;
+      } else if (s.sweeps >= max_sweeps) {
+        stop = true;
+      } else if (guard && s.sweeps >= 4 && rho < 100.0 * tol && rho > 0.99 * s.hist[0] &&
+                 s.hist[0] > 0.99 * s.hist[1] && s.hist[1] > 0.99 * s.hist[2]) {
+        s.floor_limited = 1;
+        stop = true;
+      }
+      s.hist[2] = s.hist[1];
+      s.hist[1] = s.hist[0];
+      s.hist[0] = rho;
+      state[i] = s;
+      if (stop) active[i] = 0;
+    }
+    __threadfence();
+    last = (atomicAdd(ticket, 1) == n - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    int cnt = 0;
+    for (int k = 0; k < n; ++k) cnt += __atomic_load_n(&active[k], __ATOMIC_RELAXED);
+    active[n] = cnt;
+    *ticket = 0;
+  }
+}
+
+hipError_t batch_check(const double* red, const int* red_off, int n, int* active,
+                       BatchState* state, double tol, int max_sweeps, int guard, hipStream_t st) {
+  hipLaunchKernelGGL(batch_check_kernel, dim3(n), dim3(256), 0, st, red, red_off, n, active,
+                     state, tol, max_sweeps, guard, active + n + 1);
+  return hipGetLastError();
+}
+
+__global__ void batch_reset_kernel(int* active, BatchState* state, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    active[i] = 1;
+    BatchState s;
+    s.sweeps = s.converged = s.floor_limited = s.pad = 0;
+    s.residual = 0.0;
+    s.hist[0] = s.hist[1] = s.hist[2] = INFINITY;
+    state[i] = s;
+  }
+  if (i == 0) {
+    active[n] = n;
+    active[n + 1] = 0;
+  }
+}
+
+hipError_t batch_reset(int* active, BatchState* state, int n, hipStream_t st) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, st, active, state,
+                     n);
   return hipGetLastError();
 }
 

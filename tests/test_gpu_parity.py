@@ -268,3 +268,15 @@ def test_sweep_entry_point_matches_solve(ib):
         assert torch.equal(H, h_solve), prec
         assert res[-1] == pytest.approx(plan.residual(H), rel=1e-12)
         plan.close()
+
+
+def test_progress_callback_can_stop(ib):
+    _say("progress callback cancels after 3 sweeps")
+    A = workloads.config2_matrix(p=700)
+    plan = ib.Plan(_dev(A), block_rows=200, overlap=24, tol=1e-14, max_sweeps=50)
+    seen = []
+    out = plan.solve(progress=lambda r, res, sv: seen.append((r, res)) or r >= 3)
+    assert out.sweeps == 3 and out.cancelled and not out.converged
+    assert [r for r, _ in seen] == [1, 2, 3]
+    assert seen[-1][1] == out.residual
+    plan.close()
