@@ -25,6 +25,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PANEL_KERNEL = "gemm_kernel<double, 64, 64, 16, 2, 2, 1, 2>"
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per panel launch from the committed rocprofv3 PMC summary, if it was taken
+    on the same kernel instantiation the bench runs; None otherwise."""
+    import re
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "panel_gemm_p16384_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    k = re.search(r"^kernel:\s*(.+)$", text, re.M)
+    if not m or not k or k.group(1).strip() != kernel:
+        return None
+    return float(m.group(1))
+
+
 def cpu_baseline(A, ranges, n_sets):
     """The oracle, untouched, on a bounded sample of the same workload: the factors and the
     eq. (IBMI) updates of the first n_sets sets of the first sweep from H = I."""
@@ -94,6 +114,8 @@ def main():
     ap.add_argument("--p", type=int, default=16384)
     ap.add_argument("--full-solve", action="store_true")
     ap.add_argument("--max-sweeps", type=int, default=3000)
+    ap.add_argument("--full-solve-forms", default="fp64,fp32",
+                    help="comma-separated forms for --full-solve")
     ap.add_argument("--batched", action="store_true",
                     help="also time the batched form on 256 matrices, p log-uniform in [128, 2048]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -159,6 +181,7 @@ def main():
                     "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 else None}
                 for c, v in kt.items()}
 
+    panel_cfg_default = "IBMI_CFG_PANEL" not in os.environ
     plan, ranges, plan_s, dt, kt, hist = run_form("fp64")
     K = len(ranges)
     f_sweep = oracle.flops_sweep(p, ranges)
@@ -180,9 +203,11 @@ def main():
         "plan_s": round(plan_s, 4),
         "plan_tflops": round(f_plan / plan_s / 1e12, 3),
         "kernels": kernels_json(kt),
-        "roofline": {"kernel": "gemm_kernel<double> panel epilogue (W H[I^c,I^c] -> H)",
+        "roofline": {"kernel": PANEL_KERNEL + " (W H[I^c,I^c] scattered into H)",
                      "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(PANEL_KERNEL) if panel_cfg_default else None,
+                     "traffic_unit": "bytes per launch"},
         "residual_rate_per_sweep": round(rate, 5) if rate else None,
     }
     plan.close()
@@ -202,7 +227,8 @@ def main():
         plan = None
     if args.full_solve:
         out["full_solve"] = {}
-        for prec in ("fp64", "fp32"):
+        forms = [f for f in args.full_solve_forms.split(",") if f]
+        for prec in forms:
             log(f"[{prec}] full solve to relative-error bound 1e-10")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -216,9 +242,9 @@ def main():
                 return False
 
             sol = fplan.solve(H, progress=progress)
-            if prec == "fp64":
+            if prec == "fp64" and len(forms) > 1:
                 H64 = H.clone()
-            else:
+            elif prec == "fp32" and "fp64" in forms:
                 diff = float(torch.linalg.norm(H - H64) / torch.linalg.norm(H64))
                 out["full_solve"]["fp32_vs_fp64_rel_fro"] = diff
                 del H64

@@ -73,8 +73,8 @@ typedef struct {
   double tol;              /* > 0                                                          */
   double lambda_min;       /* > 0 when stop = REL_BOUND                                    */
   int32_t max_sweeps;      /* >= 1; hitting it is not an error (converged = 0)             */
-  int32_t stagnation_guard;/* 1: stop (floor_limited = 1) when the residual fell < 1% in   */
-                           /*    each of the last 3 sweeps while already below 100 tol     */
+  int32_t stagnation_guard;/* 1: stop (floor_limited = 1) once the best residual is below   */
+                           /*    100 tol and 4 sweeps in a row failed to improve it by 1%  */
   int32_t fixed_sweeps;    /* > 0: run exactly this many sweeps, ignore tol and the guard  */
   int32_t reserved;
 } ibmi_options;

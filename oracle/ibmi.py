@@ -201,8 +201,9 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     ||I - A H||_F / (lam_min ||H||_F) < tol (a certified bound on the relative error of H
     when lam_min is a lower bound on A's smallest eigenvalue).  The loop always runs at
     least one sweep, and returns H after ``max_sweeps`` with converged=False when the test
-    never passes.  Stagnation guard: stop with floor_limited=True when the residual fell by
-    less than 1% in each of the last three sweeps and is already below 100 tol.
+    never passes.  Stagnation guard (the FP64 floor of ||I - A H||_F can lie above tol):
+    stop with floor_limited=True once the best residual so far is below 100 tol and no sweep
+    has improved on it by at least 1% for four sweeps in a row.
     ``fixed_sweeps > 0`` runs exactly that many sweeps (parity at equal sweep counts).
     """
     if tol <= 0 or max_sweeps < 1:
@@ -211,6 +212,7 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     h = initial_h(a, bp, init, h0)
     res = SolveResult(h, 0)
     limit = fixed_sweeps if fixed_sweeps > 0 else max_sweeps
+    best, since_best = float("inf"), 0
     while True:
         res.sweeps += 1
         sweep(h, bp)
@@ -218,6 +220,10 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
         if not np.isfinite(rho):
             raise IbmiError("NONFINITE", f"residual is not finite after sweep {res.sweeps}")
         res.history.append(rho)
+        if rho < 0.99 * best:
+            best, since_best = rho, 0
+        else:
+            since_best += 1
         if fixed_sweeps > 0:
             if res.sweeps >= limit:
                 res.converged = _stop_value(a, h, rho, stop, lam_min) < tol
@@ -228,9 +234,7 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
             break
         if res.sweeps >= limit:
             break
-        hist = res.history
-        if (stagnation_guard and len(hist) >= 4 and rho < 100.0 * tol
-                and all(hist[-j] > 0.99 * hist[-j - 1] for j in (1, 2, 3))):
+        if stagnation_guard and best < 100.0 * tol and since_best >= 4:
             res.floor_limited = True
             break
     return res

@@ -95,8 +95,11 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   static_assert(XV * VEC == XE && YV * VEC == YE && BM % VEC == 0 && BN % VEC == 0, "bad VEC");
   static_assert(TM * 16 == WTM && TN * 16 == WTN && BK % 4 == 0, "bad wave tile");
 
-  __shared__ __attribute__((aligned(16))) T Xs[2][BK][BM];
-  __shared__ __attribute__((aligned(16))) T Ys[2][BK][BN];
+  // FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction; padding each
+  // row by 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left unpadded.
+  constexpr int PAD = sizeof(T) == 4 ? 16 : 0;
+  __shared__ __attribute__((aligned(16))) T Xs[2][BK][BM + PAD];
+  __shared__ __attribute__((aligned(16))) T Ys[2][BK][BN + PAD];
   __shared__ double red_s[NT / 64];
 
   const int tid = threadIdx.x;

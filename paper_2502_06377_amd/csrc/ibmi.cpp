@@ -648,7 +648,8 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
   if (rc != IBMI_OK) return rc;
   const int limit = o.fixed_sweeps > 0 ? o.fixed_sweeps : o.max_sweeps;
   const bool want_h = o.stop == IBMI_STOP_REL_BOUND;
-  std::vector<double> hist;
+  double best = INFINITY;
+  int since_best = 0;
   while (true) {
     double r2 = 0.0, h2 = 0.0;
     rc = sweep_once(plan, dH, ldh, info->sweeps == 0, want_h, &r2, &h2);
@@ -657,8 +658,13 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
     const double rho = std::sqrt(r2);
     info->residual = rho;
     if (!std::isfinite(rho)) return IBMI_ERR_NONFINITE;
-    hist.push_back(rho);
     if (history) history[info->sweeps - 1] = rho;
+    if (rho < 0.99 * best) {
+      best = rho;
+      since_best = 0;
+    } else {
+      ++since_best;
+    }
     const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
     info->stop_value = sv;
     if (plan->progress && plan->progress(info->sweeps, rho, sv, plan->progress_user) != 0) {
@@ -678,9 +684,7 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
       break;
     }
     if (info->sweeps >= limit) break;
-    const size_t n = hist.size();
-    if (o.stagnation_guard && n >= 4 && rho < 100.0 * o.tol && hist[n - 1] > 0.99 * hist[n - 2] &&
-        hist[n - 2] > 0.99 * hist[n - 3] && hist[n - 3] > 0.99 * hist[n - 4]) {
+    if (o.stagnation_guard && best < 100.0 * o.tol && since_best >= 4) {
       info->floor_limited = 1;
       break;
     }

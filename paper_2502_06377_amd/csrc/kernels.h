@@ -80,9 +80,9 @@ struct FinTask {
 
 // Per-matrix state of a batched solve.
 struct BatchState {
-  int32_t sweeps, converged, floor_limited, pad;
+  int32_t sweeps, converged, floor_limited, since_best;
   double residual;
-  double hist[3];
+  double best;
 };
 
 // Tile configurations of the MFMA GEMM: workgroup tile, waves, and the number of

@@ -439,14 +439,18 @@ __global__ void __launch_bounds__(256) batch_check_kernel(const double* red, con
         stop = true;
       } else if (s.sweeps >= max_sweeps) {
         stop = true;
-      } else if (guard && s.sweeps >= 4 && rho < 100.0 * tol && rho > 0.99 * s.hist[0] &&
-                 s.hist[0] > 0.99 * s.hist[1] && s.hist[1] > 0.99 * s.hist[2]) {
-        s.floor_limited = 1;
-        stop = true;
+      } else {
+        if (rho < 0.99 * s.best) {
+          s.best = rho;
+          s.since_best = 0;
+        } else {
+          s.since_best += 1;
+        }
+        if (guard && s.best < 100.0 * tol && s.since_best >= 4) {
+          s.floor_limited = 1;
+          stop = true;
+        }
       }
-      s.hist[2] = s.hist[1];
-      s.hist[1] = s.hist[0];
-      s.hist[0] = rho;
       state[i] = s;
       if (stop) active[i] = 0;
     }
@@ -475,9 +479,9 @@ __global__ void batch_reset_kernel(int* active, BatchState* state, int n) {
   if (i < n) {
     active[i] = 1;
     BatchState s;
-    s.sweeps = s.converged = s.floor_limited = s.pad = 0;
+    s.sweeps = s.converged = s.floor_limited = s.since_best = 0;
     s.residual = 0.0;
-    s.hist[0] = s.hist[1] = s.hist[2] = INFINITY;
+    s.best = INFINITY;
     state[i] = s;
   }
   if (i == 0) {

@@ -43,6 +43,7 @@ class Result:
     footprint: int
     H: torch.Tensor | None = None
     error: str | None = None
+    floor_limited: bool = False
 
     @property
     def latency(self) -> float:
@@ -96,7 +97,10 @@ class ServeStats:
                 "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
                 "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
                 "latency_max_s": round(float(lat.max()), 4),
-                "all_converged": all(r.converged for r in self.results),
+                "converged": sum(r.converged for r in self.results),
+                "floor_limited": sum(r.floor_limited for r in self.results),
+                "capped_or_failed": sum(not (r.converged or r.floor_limited)
+                                        for r in self.results),
                 "errors": [r.error for r in self.results if r.error][:5],
                 "max_hbm_in_use_bytes": self.max_in_use, "hbm_budget_bytes": budget,
                 "max_queue_depth": self.max_queue}
@@ -106,7 +110,7 @@ class ServeLoop:
     """Continuous-batching server over `slots` concurrent streams within `hbm_budget` bytes."""
 
     def __init__(self, slots: int = 4, hbm_budget: int = 64 << 30, block_rows: int = 576,
-                 overlap: int = 64, max_sweeps: int = 3000, keep_h: bool = False,
+                 overlap: int = 64, max_sweeps: int = 500, keep_h: bool = False,
                  device="cuda:0", progress: bool = False):
         self.progress = progress
         self.slots = slots
@@ -138,7 +142,8 @@ class ServeLoop:
             stream.synchronize()
         end = time.perf_counter()
         return Result(req.rid, req.p, req.tol, form, arrival_abs, start, end, out.sweeps,
-                      out.converged, out.residual, fp, H if self.keep_h else None)
+                      out.converged, out.residual, fp, H if self.keep_h else None,
+                      floor_limited=out.floor_limited)
 
     def run(self, requests, time_scale: float = 1.0, max_wall: float | None = None) -> ServeStats:
         """Replay ``requests`` (with arrival_s fields) in real time scaled by ``time_scale``."""

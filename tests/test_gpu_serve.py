@@ -38,8 +38,9 @@ def test_serve_mix_equals_alone(srv):
     stats = loop.run(reqs)
     assert len(stats.results) == len(reqs)
     assert stats.max_in_use <= budget
-    bad = [(r.rid, r.p, r.form, r.sweeps, r.residual, getattr(r, "error", None))
-           for r in stats.results if not r.converged]
+    # a request either meets its tolerance or stops at its FP64 floor (stagnation guard)
+    bad = [(r.rid, r.p, r.form, r.sweeps, r.residual, r.error)
+           for r in stats.results if not (r.converged or r.floor_limited)]
     assert not bad, bad
     by_id = {r.rid: r for r in stats.results}
     for rid in (0, 3, 8, 13):
@@ -48,15 +49,15 @@ def test_serve_mix_equals_alone(srv):
         ld = (req.p + 7) // 8 * 8
         H = torch.empty((req.p, ld), dtype=torch.float64, device="cuda:0")[:, :req.p]
         plan = ib.Plan(A, block_rows=256, overlap=32, precision=res.form, tol=req.tol,
-                       max_sweeps=3000)
+                       max_sweeps=500)
         out = plan.solve(H)
         plan.close()
         torch.cuda.synchronize()
         assert out.sweeps == res.sweeps
         diff = float(torch.linalg.norm(out.H - res.H) / torch.linalg.norm(out.H))
         assert diff <= 1e-12, (rid, diff)
-        if req.tol < 1e-6:
-            inv = torch.linalg.inv(A.cpu()).numpy()
-            assert np.linalg.norm(res.H.cpu().numpy() - inv) / np.linalg.norm(inv) < 1e-8
+        inv = torch.linalg.inv(A.cpu()).numpy()
+        rel = np.linalg.norm(res.H.cpu().numpy() - inv) / np.linalg.norm(inv)
+        assert rel < (1e-8 if req.tol < 1e-6 else 1e-4), (rid, rel)
     s = stats.summary(len(reqs), budget)
     assert s["latency_p99_s"] >= s["latency_p50_s"] > 0

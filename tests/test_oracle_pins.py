@@ -381,3 +381,16 @@ def test_fp32_correction_form_refines_to_fp64_accuracy():
         oracle.correction_sweep(A, H, P, "fp32")
     ref = np.linalg.inv(A)
     assert _rel(H, ref) < 1e-10
+
+
+def test_stagnation_guard_stops_at_the_floor():
+    """A tolerance below the FP64 floor of ||I - A H||_F ends with floor_limited, not at the
+    cap; the same matrix with a reachable tolerance converges."""
+    A = workloads.config2_matrix(p=1500)
+    ranges = oracle.partition(1500, 576, 64)
+    res = oracle.ibmi_solve(A, ranges, tol=1e-11, max_sweeps=500)  # floor here: 2.9e-10
+    assert res.floor_limited and not res.converged and res.sweeps < 30
+    best = min(res.history)
+    assert best < 100 * 1e-11 and all(h > 0.99 * best for h in res.history[-4:])
+    res2 = oracle.ibmi_solve(A, ranges, tol=1e-8, max_sweeps=500)
+    assert res2.converged and not res2.floor_limited
