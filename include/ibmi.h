@@ -73,8 +73,9 @@ typedef struct {
   double tol;              /* > 0                                                          */
   double lambda_min;       /* > 0 when stop = REL_BOUND                                    */
   int32_t max_sweeps;      /* >= 1; hitting it is not an error (converged = 0)             */
-  int32_t stagnation_guard;/* 1: stop (floor_limited = 1) once the best residual is below   */
-                           /*    100 tol and 4 sweeps in a row failed to improve it by 1%  */
+  int32_t stagnation_guard;/* 1: stop (floor_limited = 1) once the best stop value (the     */
+                           /*    quantity compared with tol) is below 100 tol and 4 sweeps */
+                           /*    in a row failed to improve it by 1%                       */
   int32_t fixed_sweeps;    /* > 0: run exactly this many sweeps, ignore tol and the guard  */
   int32_t reserved;
 } ibmi_options;
@@ -209,7 +210,7 @@ ibmi_status ibmi_batch_plan(ibmi_batch_t* out, int32_t n, const int64_t* p,
 ibmi_status ibmi_batch_solve(ibmi_batch_t batch, double* const* dH, const int64_t* ldh,
                              ibmi_info* infos);
 
-/* Tile configurations (0 <= cfg < 10; see the GEMM configuration table in the sources) of
+/* Tile configurations (0 <= cfg < 11; see the GEMM configuration table in the sources) of
  * the grouped panel, diagonal and residual launches. */
 ibmi_status ibmi_batch_set_tuning(ibmi_batch_t batch, int32_t panel, int32_t diag,
                                   int32_t resid);

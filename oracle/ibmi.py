@@ -202,8 +202,9 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     when lam_min is a lower bound on A's smallest eigenvalue).  The loop always runs at
     least one sweep, and returns H after ``max_sweeps`` with converged=False when the test
     never passes.  Stagnation guard (the FP64 floor of ||I - A H||_F can lie above tol):
-    stop with floor_limited=True once the best residual so far is below 100 tol and no sweep
-    has improved on it by at least 1% for four sweeps in a row.
+    stop with floor_limited=True once the best stop value so far (the quantity compared with
+    tol) is below 100 tol and no sweep has improved on it by at least 1% for four sweeps in a
+    row.
     ``fixed_sweeps > 0`` runs exactly that many sweeps (parity at equal sweep counts).
     """
     if tol <= 0 or max_sweeps < 1:
@@ -220,16 +221,17 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
         if not np.isfinite(rho):
             raise IbmiError("NONFINITE", f"residual is not finite after sweep {res.sweeps}")
         res.history.append(rho)
-        if rho < 0.99 * best:
-            best, since_best = rho, 0
+        sv = _stop_value(a, h, rho, stop, lam_min)
+        if sv < 0.99 * best:
+            best, since_best = sv, 0
         else:
             since_best += 1
         if fixed_sweeps > 0:
             if res.sweeps >= limit:
-                res.converged = _stop_value(a, h, rho, stop, lam_min) < tol
+                res.converged = sv < tol
                 break
             continue
-        if _stop_value(a, h, rho, stop, lam_min) < tol:
+        if sv < tol:
             res.converged = True
             break
         if res.sweeps >= limit:

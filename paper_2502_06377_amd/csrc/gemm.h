@@ -284,7 +284,8 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   X_(GEMM_64x64_W1, 64, 64, 16, 1, 1)                                                          \
   X_(GEMM_32x64_W1, 32, 64, 16, 1, 1)                                                          \
   X_(GEMM_64x64_W2, 64, 64, 32, 2, 1)                                                          \
-  X_(GEMM_96x128, 96, 128, 32, 2, 2)
+  X_(GEMM_96x128, 96, 128, 32, 2, 2)                                                           \
+  X_(GEMM_192x96, 192, 96, 16, 2, 2)
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ>
 __global__ void __launch_bounds__(64 * WM * WN)

@@ -659,14 +659,15 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
     info->residual = rho;
     if (!std::isfinite(rho)) return IBMI_ERR_NONFINITE;
     if (history) history[info->sweeps - 1] = rho;
-    if (rho < 0.99 * best) {
-      best = rho;
+    const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
+    info->stop_value = sv;
+    // Stagnation guard, in the units of the stop test.
+    if (sv < 0.99 * best) {
+      best = sv;
       since_best = 0;
     } else {
       ++since_best;
     }
-    const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
-    info->stop_value = sv;
     if (plan->progress && plan->progress(info->sweeps, rho, sv, plan->progress_user) != 0) {
       info->cancelled = 1;
       info->converged = o.fixed_sweeps > 0 ? 0 : (sv < o.tol);

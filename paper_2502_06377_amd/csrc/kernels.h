@@ -98,7 +98,8 @@ enum GemmCfg {
   GEMM_32x64_W1 = 7,    // 1 wave of 32x64    ( 8 chains), BK 16
   GEMM_64x64_W2 = 8,    // 2x1 waves of 32x64 ( 8 chains), BK 32
   GEMM_96x128 = 9,      // 2x2 waves of 48x64 (12 chains), BK 32
-  GEMM_CFG_COUNT = 10
+  GEMM_192x96 = 10,     // 2x2 waves of 96x48 (18 chains), BK 16
+  GEMM_CFG_COUNT = 11
 };
 struct GemmDims {
   int bm, bn;

@@ -394,3 +394,16 @@ def test_stagnation_guard_stops_at_the_floor():
     assert best < 100 * 1e-11 and all(h > 0.99 * best for h in res.history[-4:])
     res2 = oracle.ibmi_solve(A, ranges, tol=1e-8, max_sweeps=500)
     assert res2.converged and not res2.floor_limited
+
+
+def test_stagnation_guard_works_in_the_stop_test_units():
+    """With the relative-error bound as stop test the guard compares that bound (not the
+    residual, which sits near 3e-10 here) with 100 tol: a bound tolerance below the floor the
+    bound reaches (about 1.3e-11) ends with floor_limited."""
+    A = workloads.config2_matrix(p=1500)
+    ranges = oracle.partition(1500, 576, 64)
+    res = oracle.ibmi_solve(A, ranges, tol=1e-12, stop="rel_bound", lam_min=1e-2,
+                            max_sweeps=500)
+    bound = res.history[-1] / (1e-2 * np.linalg.norm(res.h))
+    assert res.floor_limited and not res.converged and res.sweeps < 40
+    assert 1e-12 < bound < 100 * 1e-12
