@@ -3,14 +3,15 @@
 A step is one IBMI sweep of the whole hot path: the block update of eq. (IBMI) for all 32
 sets (panel GEMM W H[I^c,I^c] scattered into H, split-K diagonal product and H[I,I]
 finalisation) followed by the ||I - A H||_F check with its host read-back.  The FP64 form is
-the headline value; the FP32-update (correction) form is timed the same way and reported
-beside it, with its speedup per sweep.  Plan time (block
+the headline value; the low-precision update forms (FP32, split-bfloat16 bf16x3 and bf16x6,
+all in the correction form) are timed the same way and reported beside it, each with its
+speedup per sweep and the roofline of its update product.  Plan time (block
 factors, once per solve) is reported separately.  Inputs are synthetic: 16384 seeded
 uniform points in the unit square sorted by x, SE kernel with length scale 0.05 plus a
 1e-3 nugget, FP64, resident in HBM before timing starts.
 
-Prints ONE JSON line.  `--full-solve` additionally runs a complete solve to a relative-error
-bound of 1e-10 (certified by ||I - A H||_F / (nugget ||H||_F)) and reports s/solve.
+Prints ONE JSON line.  `--full-solve` additionally runs complete solves to a relative error
+of 1e-10, certified by the bound from ||H (I - A H)||_F, and reports s/solve per form.
 """
 import argparse
 import json
@@ -26,6 +27,13 @@ def log(msg):
 
 
 PANEL_KERNEL = "gemm_kernel<double, 64, 64, 16, 2, 2, 1, 2>"
+# Update product of each low-precision form: (dense matrix-core peak of the instruction type
+# used, matrix-core products executed per FP32-level product, instruction type, kernel).
+UPDATE_KERNELS = {
+    "fp32": (157.3, 1, "f32", "gemm_kernel<float, 64, 64, 32, 2, 2, 5, 4> (R[I,:] - A[I,:] D)"),
+    "bf16x3": (2500.0, 3, "bf16", "split_gemm_kernel<96, 128, 32, 2, 2, 2> (R[I,:] - A[I,:] D)"),
+    "bf16x6": (2500.0, 6, "bf16", "split_gemm_kernel<96, 128, 32, 2, 2, 3> (R[I,:] - A[I,:] D)"),
+}
 
 
 def measured_traffic(kernel: str):
@@ -114,12 +122,14 @@ def main():
     ap.add_argument("--p", type=int, default=16384)
     ap.add_argument("--full-solve", action="store_true")
     ap.add_argument("--max-sweeps", type=int, default=3000)
-    ap.add_argument("--full-solve-forms", default="fp64,fp32",
+    ap.add_argument("--full-solve-forms", default="fp64,fp32,bf16x3",
                     help="comma-separated forms for --full-solve")
     ap.add_argument("--batched", action="store_true",
                     help="also time the batched form on 256 matrices, p log-uniform in [128, 2048]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-forms", default="fp32,bf16x3,bf16x6",
+                    help="low-precision update forms timed beside the FP64 form")
     ap.add_argument("--cpu-sets", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for HBM counters)")
@@ -211,30 +221,35 @@ def main():
         "residual_rate_per_sweep": round(rate, 5) if rate else None,
     }
     plan.close()
-    if not args.no_mixed:
-        mplan, _, mplan_s, mdt, mkt, mhist = run_form("fp32")
+    forms = [] if args.no_mixed else [f for f in args.mixed_forms.split(",") if f]
+    for form in forms:
+        mplan, _, mplan_s, mdt, mkt, mhist = run_form(form)
         mms = mdt / args.steps * 1e3
-        out["fp32_update_form"] = {
+        peak_m, mult, mfma_type, kname = UPDATE_KERNELS[form]
+        u_ms, u_n, u_fl = mkt["panel"]
+        u_ach = mult * u_fl / (u_ms * 1e-3) / 1e12 if u_ms > 0 else 0.0
+        out[f"{form}_update_form"] = {
             "ms_per_step": round(mms, 3), "sweeps_per_s": round(1e3 / mms, 4),
             "ibmi_tflops_equiv": round(f_sweep / (mms * 1e-3) / 1e12, 3),
             "speedup_vs_fp64": round(ms_step / mms, 3), "plan_s": round(mplan_s, 4),
             "kernels": kernels_json(mkt),
             "max_rel_residual_gap_vs_fp64": round(max(abs(a - b) / b for a, b in zip(mhist, hist)), 6),
+            "roofline": {"kernel": kname, "bound": "mfma", "mfma_dtype": mfma_type,
+                         "achieved": round(u_ach, 3), "peak": peak_m, "unit": "TFLOP/s",
+                         "frac": round(u_ach / peak_m, 4), "mfma_products_per_fp32_product": mult,
+                         "traffic": None},
         }
         mplan.close()
-        plan = None
-    else:
-        plan = None
+    plan = None
     if args.full_solve:
         out["full_solve"] = {}
         forms = [f for f in args.full_solve_forms.split(",") if f]
         for prec in forms:
-            log(f"[{prec}] full solve to relative-error bound 1e-10")
+            log(f"[{prec}] full solve to a certified relative error of 1e-10 (H R bound)")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fplan = ib.Plan(A, block_rows=block_rows, overlap=overlap, precision=prec,
-                            stop="rel_bound", lambda_min=nugget, tol=1e-10,
-                            max_sweeps=args.max_sweeps)
+                            stop="rel_hr", tol=1e-10, max_sweeps=args.max_sweeps)
 
             def progress(r, res, sv, prec=prec):
                 if r % 50 == 0:
@@ -244,15 +259,15 @@ def main():
             sol = fplan.solve(H, progress=progress)
             if prec == "fp64" and len(forms) > 1:
                 H64 = H.clone()
-            elif prec == "fp32" and "fp64" in forms:
+            elif prec != "fp64" and "fp64" in forms:
                 diff = float(torch.linalg.norm(H - H64) / torch.linalg.norm(H64))
-                out["full_solve"]["fp32_vs_fp64_rel_fro"] = diff
-                del H64
+                out["full_solve"][f"{prec}_vs_fp64_rel_fro"] = diff
             torch.cuda.synchronize()
             solve_s = time.perf_counter() - t0
             fplan.close()
             out["full_solve"][prec] = {"s_per_solve": round(solve_s, 2), "sweeps": sol.sweeps,
                                        "converged": sol.converged,
+                                       "bound_evaluations": sol.evaluations,
                                        "floor_limited": sol.floor_limited,
                                        "stop_value": sol.stop_value, "residual": sol.residual}
             log(f"[{prec}] full solve: {sol.sweeps} sweeps, {solve_s:.1f} s, "

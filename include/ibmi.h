@@ -45,21 +45,42 @@ typedef enum {
   IBMI_ERR_NONFINITE = 5      /* the residual became NaN or Inf                          */
 } ibmi_status;
 
-/* Arithmetic of the H-update products.  FP64 everywhere is the paper's method.  The
- * FP32 form runs the update products in FP32 on the matrix cores (FP32 accumulation) in
- * the correction form driven by an FP64 residual; block factors and the residual stay FP64. */
-typedef enum { IBMI_PREC_FP64 = 0, IBMI_PREC_FP32_UPDATE = 1 } ibmi_precision;
+/* Arithmetic of the H-update products.  FP64 everywhere is the paper's method.  The other
+ * forms run the large update product of each set in low precision on the matrix cores, in
+ * the correction form of the same block update driven by an FP64 residual (the change made
+ * to H since the residual was taken is what enters the low-precision product, so its error
+ * shrinks with the iteration); block factors, the small products and the residual stay FP64.
+ *   FP32_UPDATE  : FP32 operands, FP32 products and accumulation.
+ *   BF16X3_UPDATE: each FP32 operand split into two bfloat16 terms, three bf16 products
+ *                  (dropping lo*lo), FP32 accumulation: about 16 significant bits.
+ *   BF16X6_UPDATE: three bfloat16 terms, six products: about FP32's 24 bits. */
+typedef enum {
+  IBMI_PREC_FP64 = 0,
+  IBMI_PREC_FP32_UPDATE = 1,
+  IBMI_PREC_BF16X3_UPDATE = 2,
+  IBMI_PREC_BF16X6_UPDATE = 3
+} ibmi_precision;
 
 /* Initial approximation (Algorithm 1 input; only H0[I_1^c, I_1^c] is read).
  * IDENTITY is the paper's default choice.  BLOCKDIAG_INV sets H0 = blockdiag(A_{I_k}^{-1})
  * and needs disjoint sets.  GIVEN uses the caller's H as passed to ibmi_solve (resume). */
 typedef enum { IBMI_INIT_IDENTITY = 0, IBMI_INIT_BLOCKDIAG_INV = 1, IBMI_INIT_GIVEN = 2 } ibmi_init;
 
-/* Stop test after each sweep.  FRO: ||I - A H||_F < tol.  REL_BOUND:
- * ||I - A H||_F / (lambda_min * ||H||_F) < tol, a bound on the relative Frobenius error of
- * H when lambda_min is a lower bound on the smallest eigenvalue of A (e.g. the nugget of a
- * covariance matrix). */
-typedef enum { IBMI_STOP_FRO = 0, IBMI_STOP_REL_BOUND = 1 } ibmi_stop;
+/* Stop test after each sweep, on R = I - A H.
+ * FRO:       ||R||_F < tol.
+ * REL_BOUND: ||R||_F / (lambda_min * ||H||_F) < tol, a bound on the relative Frobenius error
+ *            of H when lambda_min is a lower bound on the smallest eigenvalue of A (e.g. the
+ *            nugget of a covariance matrix).  Loose by up to cond(A) for rounding errors.
+ * REL_HR:    x / (1 - x) < tol with x = ||H R||_F / ((1 - ||R||_F) ||H||_F), also a bound on
+ *            the relative Frobenius error of H (from E (R - I) = H R for E = H - A^{-1}, valid
+ *            when ||R||_F < 1) and tight to first order in ||R||.  It costs a second p^3
+ *            product, so it is evaluated only at some sweeps: the first with ||R||_F < 1, each
+ *            one at which ||R||_F has fallen tenfold since the last evaluation, and each one at
+ *            which (last bound / last ||R||_F) * ||R||_F is below tol; the stop value of the
+ *            other sweeps is that prediction (inf before the first evaluation), and only an
+ *            evaluated bound can stop the solve.  With fixed_sweeps the last sweep is
+ *            evaluated.  Needs p * p * 8 more workspace bytes in the FP64 form. */
+typedef enum { IBMI_STOP_FRO = 0, IBMI_STOP_REL_BOUND = 1, IBMI_STOP_REL_HR = 2 } ibmi_stop;
 
 typedef struct {
   int64_t p;               /* order of A                                                  */
@@ -88,7 +109,7 @@ typedef struct {
   double residual;         /* ||I - A H||_F after the last sweep                           */
   double stop_value;       /* the quantity compared with tol                               */
   int32_t cancelled;       /* 1 if the progress callback ended the solve early             */
-  int32_t reserved;
+  int32_t evaluations;     /* sweeps at which the REL_HR bound was evaluated               */
 } ibmi_info;
 
 typedef struct ibmi_plan_s* ibmi_plan_t;

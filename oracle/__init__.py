@@ -9,8 +9,8 @@ Symmetric Positive Definite Matrices with Applications to Covariance Matrices"):
   blocks of m+2h rows);
 * ``ibmi``       -- the block update of eq. (IBMI), Algorithm 1 (sweeps over k = 1..K using
   the most recent approximation), the residual ||I - A H||_F, the paper's error estimate of
-  eq. (error), and a correction (defect) form of the same update with emulated
-  low-precision products;
+  eq. (error), a certified bound on the relative error of H from ||H (I - A H)||_F, and a
+  correction (defect) form of the same update with emulated low-precision products;
 * ``cholinv``    -- the Cholesky-based direct inverse of the introduction, written out with
   loops (A = L L^T, then L z_i = e_i and L^T h_i = z_i);
 * ``exact``      -- IBMI in exact rational arithmetic for tiny matrices.
@@ -25,7 +25,7 @@ unpinned" except where a docstring says so.
 from .partition import partition, validate_blocks, complement
 from .ibmi import (
     IbmiError, plan, block_factors, initial_h, block_update, sweep, residual_fro, paper_error,
-    ibmi_solve, flops_plan, flops_sweep, correction_sweep, emulate_product,
+    ibmi_solve, flops_plan, flops_sweep, correction_sweep, emulate_product, hr_error_bound,
 )
 from .cholinv import cholesky_inverse_loops
 from .exact import exact_ibmi, exact_residual_sq

@@ -174,6 +174,24 @@ def paper_error(a: np.ndarray, h: np.ndarray, idx: np.ndarray) -> float:
     return float(np.linalg.norm(e, 2))
 
 
+def hr_error_bound(a: np.ndarray, h: np.ndarray) -> tuple:
+    """Certified bound on the relative Frobenius error of H as an inverse of A, from R = I - A H.
+
+    With E = H - A^{-1}: A^{-1} R = A^{-1} - H = -E and A^{-1} = H - E, so E (R - I) = H R and,
+    when ||R||_2 <= ||R||_F < 1, ||E||_F <= ||H R||_F / (1 - ||R||_F) =: x ||H||_F.  Since
+    ||A^{-1}||_F >= ||H||_F - ||E||_F, the relative error is at most x / (1 - x).  Returns
+    (bound, ||R||_F); the bound is inf when ||R||_F >= 1 or x >= 1.  Exact-arithmetic bound:
+    the FP64 evaluation of R limits it near the FP64 floor.
+    """
+    r = np.eye(a.shape[0]) - a @ h
+    rho = float(np.sqrt(np.sum(r * r)))
+    if rho >= 1.0:
+        return float("inf"), rho
+    hr = h @ r
+    x = float(np.sqrt(np.sum(hr * hr))) / ((1.0 - rho) * float(np.sqrt(np.sum(h * h))))
+    return (x / (1.0 - x) if x < 1.0 else float("inf")), rho
+
+
 @dataclass
 class SolveResult:
     h: np.ndarray
@@ -181,6 +199,8 @@ class SolveResult:
     history: list = field(default_factory=list)
     converged: bool = False
     floor_limited: bool = False
+    stop_value: float = float("inf")  # after the last sweep
+    evaluations: int = 0              # sweeps at which the rel_hr bound was evaluated
 
 
 def _stop_value(a, h, rho, stop, lam_min):
@@ -199,7 +219,12 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
 
     ``stop="fro"`` stops once ||I - A H||_F < tol; ``stop="rel_bound"`` once
     ||I - A H||_F / (lam_min ||H||_F) < tol (a certified bound on the relative error of H
-    when lam_min is a lower bound on A's smallest eigenvalue).  The loop always runs at
+    when lam_min is a lower bound on A's smallest eigenvalue); ``stop="rel_hr"`` once the
+    bound of hr_error_bound (from ||H R||_F, tight to first order) is below tol.  That bound
+    costs a second p^3 product, so it is evaluated only at some sweeps: when ||R||_F < 1 for
+    the first time, when ||R||_F has fallen tenfold since the last evaluation, and when the
+    last evaluation's ratio bound/||R||_F times the current ||R||_F is below tol; at other
+    sweeps the stop value is that prediction (inf before the first evaluation).  The loop always runs at
     least one sweep, and returns H after ``max_sweeps`` with converged=False when the test
     never passes.  Stagnation guard (the FP64 floor of ||I - A H||_F can lie above tol):
     stop with floor_limited=True once the best stop value so far (the quantity compared with
@@ -214,6 +239,7 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     res = SolveResult(h, 0)
     limit = fixed_sweeps if fixed_sweeps > 0 else max_sweeps
     best, since_best = float("inf"), 0
+    ratio, rho_eval = None, None
     while True:
         res.sweeps += 1
         sweep(h, bp)
@@ -221,7 +247,18 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
         if not np.isfinite(rho):
             raise IbmiError("NONFINITE", f"residual is not finite after sweep {res.sweeps}")
         res.history.append(rho)
-        sv = _stop_value(a, h, rho, stop, lam_min)
+        if stop == "rel_hr":
+            last = fixed_sweeps > 0 and res.sweeps >= limit
+            due = rho < 1.0 and (ratio is None or ratio * rho < tol or rho < 0.1 * rho_eval)
+            if due or last:
+                sv, _ = hr_error_bound(a, h)
+                ratio, rho_eval = (sv / rho if rho > 0.0 else 0.0), rho
+                res.evaluations += 1
+            else:
+                sv = ratio * rho if ratio is not None else float("inf")
+        else:
+            sv = _stop_value(a, h, rho, stop, lam_min)
+        res.stop_value = sv
         if sv < 0.99 * best:
             best, since_best = sv, 0
         else:

@@ -26,14 +26,15 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ constants (ibmi.h)
 IBMI_OK, IBMI_ERR_INVALID_ARG, IBMI_ERR_NOT_SPD, IBMI_ERR_OUT_OF_MEMORY, IBMI_ERR_HIP, \
     IBMI_ERR_NONFINITE = range(6)
-IBMI_PREC_FP64, IBMI_PREC_FP32_UPDATE = 0, 1
+IBMI_PREC_FP64, IBMI_PREC_FP32_UPDATE, IBMI_PREC_BF16X3_UPDATE, IBMI_PREC_BF16X6_UPDATE = 0, 1, 2, 3
 IBMI_INIT_IDENTITY, IBMI_INIT_BLOCKDIAG_INV, IBMI_INIT_GIVEN = 0, 1, 2
-IBMI_STOP_FRO, IBMI_STOP_REL_BOUND = 0, 1
+IBMI_STOP_FRO, IBMI_STOP_REL_BOUND, IBMI_STOP_REL_HR = 0, 1, 2
 
 _INIT = {"identity": IBMI_INIT_IDENTITY, "blockdiag_inv": IBMI_INIT_BLOCKDIAG_INV,
          "given": IBMI_INIT_GIVEN}
-_STOP = {"fro": IBMI_STOP_FRO, "rel_bound": IBMI_STOP_REL_BOUND}
-_PREC = {"fp64": IBMI_PREC_FP64, "fp32": IBMI_PREC_FP32_UPDATE}
+_STOP = {"fro": IBMI_STOP_FRO, "rel_bound": IBMI_STOP_REL_BOUND, "rel_hr": IBMI_STOP_REL_HR}
+_PREC = {"fp64": IBMI_PREC_FP64, "fp32": IBMI_PREC_FP32_UPDATE, "bf16x3": IBMI_PREC_BF16X3_UPDATE,
+         "bf16x6": IBMI_PREC_BF16X6_UPDATE}
 
 
 class IbmiOptions(ctypes.Structure):
@@ -49,7 +50,7 @@ class IbmiInfo(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("failed_block", ctypes.c_int32), ("floor_limited", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("stop_value", ctypes.c_double),
-                ("cancelled", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cancelled", ctypes.c_int32), ("evaluations", ctypes.c_int32)]
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -241,6 +242,7 @@ class SolveOutput:
     stop_value: float
     history: list
     cancelled: bool = False
+    evaluations: int = 0  # sweeps at which the rel_hr bound was evaluated
 
 
 class Plan:
@@ -273,7 +275,8 @@ class Plan:
             if cb is not None:
                 _lib.ibmi_set_progress(self.handle, PROGRESS_FN(), None)
         return SolveOutput(H, info.sweeps, bool(info.converged), bool(info.floor_limited),
-                           info.residual, info.stop_value, hist, bool(info.cancelled))
+                           info.residual, info.stop_value, hist, bool(info.cancelled),
+                           info.evaluations)
 
     def residual(self, H: torch.Tensor) -> float:
         return ibmi_residual(self.handle, H)

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libibmi.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["kernels.hip", "gemm_f64_a.hip", "gemm_f64_b.hip", "gemm_f32.hip", "gemm_grouped.hip",
-           "ibmi.cpp", "batch.cpp"]
+           "gemm_split.hip", "ibmi.cpp", "batch.cpp"]
 # Packed FP32 instructions are disabled on purpose for every device pass.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -539,7 +539,7 @@ ibmi_status ibmi_batch_solve(ibmi_batch_t B, double* const* dH, const int64_t* l
     infos[i].residual = hs[i].residual;
     infos[i].stop_value = hs[i].residual;
     infos[i].cancelled = 0;
-    infos[i].reserved = 0;
+    infos[i].evaluations = 0;
     if (!std::isfinite(hs[i].residual)) rc = IBMI_ERR_NONFINITE;
   }
   return rc;

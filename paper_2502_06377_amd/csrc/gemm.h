@@ -245,6 +245,8 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
           const double d = (m == n ? 1.0 : 0.0) - v;
           ea.out[m * ea.ldo + n] = d;
           ss += d * d;
+        } else if constexpr (EPI == EPI_SUMSQ) {
+          ss += v * v;
         } else if constexpr (EPI == EPI_SUBFROM) {
           ea.out[m * ea.ldo + n] = ea.src[(ea.s + m) * ea.lds + n] - v;
         } else {
@@ -261,7 +263,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
           ea.D[cn * ea.ldd + gm_] = dn;
         }
       }
-  if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_STORE) {
+  if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_STORE || EPI == EPI_SUMSQ) {
     ss = wave_sum(ss);
     if (lane == 0) red_s[wave] = ss;
     __syncthreads();
@@ -359,7 +361,9 @@ inline hipError_t launch_gemm(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N,
   if (n_tiles) *n_tiles = tiles;
   if (tiles == 0) return hipSuccess;
   const int per_xcd = (tiles + 7) / 8;
-  const int gm = EPI == EPI_RESID ? 8 : mtc;
+  // Square residual-type products walk groups of 8 row tiles; the panel and diagonal
+  // products (few row tiles) walk whole columns.
+  const int gm = (EPI == EPI_RESID || EPI == EPI_RESID_STORE || EPI == EPI_SUMSQ) ? 8 : mtc;
   const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : (K > 0 ? K : 1);
   const dim3 grid(8 * per_xcd, splits > 1 ? splits : 1);
 #define IBMI_LAUNCH(BM_, BN_, BK_, WM_, WN_)                                                   \

@@ -1,4 +1,5 @@
-// FP64 GEMM launches: residual (with optional store) and the correction epilogue.
+// FP64 GEMM launches: residual (with optional store), sum of squares of a product, and the
+// correction epilogue.
 #include "gemm.h"
 
 namespace ibmi {
@@ -13,6 +14,13 @@ hipError_t gemm_resid(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t
     return launch_gemm<double, EPI_RESID_STORE>(cfg, X, Y, M, N, K, 1, ea, st, n_red);
   }
   return launch_gemm<double, EPI_RESID>(cfg, X, Y, M, N, K, 1, ea, st, n_red);
+}
+
+hipError_t gemm_sumsq(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* red,
+                      int64_t* n_red, hipStream_t st) {
+  EpiArgs ea;
+  ea.red = red;
+  return launch_gemm<double, EPI_SUMSQ>(cfg, X, Y, M, N, K, 1, ea, st, n_red);
 }
 
 hipError_t gemm_corr(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* delta,

@@ -16,6 +16,7 @@
 
 using ibmi::BlockDesc;
 using ibmi::GemmCfg;
+using ibmi::SplitCfg;
 using ibmi::IdxMap;
 using ibmi::Opnd;
 
@@ -105,10 +106,10 @@ ibmi_status make_sets(const ibmi_options* o, std::vector<int64_t>& s, std::vecto
 ibmi_status check_options(const ibmi_options* o) {
   if (!o) return IBMI_ERR_INVALID_ARG;
   if (!(o->tol > 0.0) || o->max_sweeps < 1 || o->fixed_sweeps < 0) return IBMI_ERR_INVALID_ARG;
-  if (o->precision != IBMI_PREC_FP64 && o->precision != IBMI_PREC_FP32_UPDATE)
+  if (o->precision < IBMI_PREC_FP64 || o->precision > IBMI_PREC_BF16X6_UPDATE)
     return IBMI_ERR_INVALID_ARG;
   if (o->init < IBMI_INIT_IDENTITY || o->init > IBMI_INIT_GIVEN) return IBMI_ERR_INVALID_ARG;
-  if (o->stop != IBMI_STOP_FRO && o->stop != IBMI_STOP_REL_BOUND) return IBMI_ERR_INVALID_ARG;
+  if (o->stop < IBMI_STOP_FRO || o->stop > IBMI_STOP_REL_HR) return IBMI_ERR_INVALID_ARG;
   if (o->stop == IBMI_STOP_REL_BOUND && !(o->lambda_min > 0.0)) return IBMI_ERR_INVALID_ARG;
   return IBMI_OK;
 }
@@ -122,12 +123,16 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
 
 // Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel and
 // diagonal products favour small tiles with many resident waves, the square residual the
-// 8-wave 128x128 tile, the FP32 update the 64x64 tile.
+// 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 96x128 tiles
+// with K cut into chunks of 4096 (six row tiles of a 576-row set times four chunks fill the
+// chip where whole-K tiles leave it half idle).
 struct Tuning {
   GemmCfg panel = ibmi::GEMM_64x64_K16, diag = ibmi::GEMM_64x64_K16,
           resid = ibmi::GEMM_128x128_W8, plan = ibmi::GEMM_64x64_K16, upd32 = ibmi::GEMM_64x64,
           small = ibmi::GEMM_64x64_K16;
   int diag_splits = 0;  // 0 = automatic
+  SplitCfg split = ibmi::SPLIT_96x128;  // split-bfloat16 update product
+  int64_t split_kchunk = 4096;          // its K chunk (0: whole K per tile)
 };
 
 Tuning tuning_for(int64_t p) {
@@ -141,6 +146,11 @@ Tuning tuning_for(int64_t p) {
   t.resid = env_cfg("IBMI_CFG_RESID", t.resid);
   t.plan = env_cfg("IBMI_CFG_PLAN", t.plan);
   if (const char* v = std::getenv("IBMI_DIAG_SPLITS")) t.diag_splits = std::max(1, std::atoi(v));
+  if (const char* v = std::getenv("IBMI_CFG_SPLIT")) {
+    const int i = std::atoi(v);
+    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = (SplitCfg)i;
+  }
+  if (const char* v = std::getenv("IBMI_SPLIT_KCHUNK")) t.split_kchunk = std::max(0, std::atoi(v));
   return t;
 }
 
@@ -168,8 +178,9 @@ int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
   size_t desc = 0, fac = 0, wt = 0, part = 0, red = 0, red2 = 0, scal = 0, status = 0, total = 0;
-  // FP32-update form only (zero size otherwise)
-  size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, x2 = 0;
+  // Correction (FP32 / split-bfloat16 update) forms only (zero size otherwise)
+  size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, x2 = 0, spart = 0;
+  int64_t ld32 = 0;  // row stride of the FP32 copies of A and D (multiple of 4)
   std::vector<BlockDesc> blocks;
   std::vector<int64_t> wt_off;  // doubles, relative to wt
   int64_t b_max = 0;
@@ -216,8 +227,9 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
   off = align_up(off + 8 * 8);
   L.status = off;
   off = align_up(off + 4 * sizeof(int));
-  if (o->precision == IBMI_PREC_FP32_UPDATE) {
-    const size_t pp = (size_t)p * p;
+  if (o->precision != IBMI_PREC_FP64) {
+    L.ld32 = (p + 3) / 4 * 4;
+    const size_t pp = (size_t)p * L.ld32;
     const int64_t c_max = p - [&] {
       int64_t bmin = p;
       for (const auto& d : L.blocks) bmin = std::min(bmin, d.b);
@@ -237,6 +249,14 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
     off = align_up(off + (size_t)L.b_max * L.b_max * 8);
     L.x2 = off;
     off = align_up(off + (size_t)L.b_max * L.b_max * 8);
+    if (o->precision != IBMI_PREC_FP32_UPDATE) {
+      const int64_t chunks = ibmi::split_max_chunks(p, t.split_kchunk);
+      L.spart = off;
+      if (chunks > 1) off = align_up(off + (size_t)chunks * L.b_max * p * 4);
+    }
+  } else if (o->stop == IBMI_STOP_REL_HR) {
+    L.rt = off;  // R = I - A H of the last sweep, for the H R bound
+    off = align_up(off + (size_t)p * p * 8);
   }
   L.total = off;
   return L;
@@ -307,7 +327,13 @@ struct ibmi_plan_s {
   double* scal() const { return (double*)(work + L.scal); }
   int* status() const { return (int*)(work + L.status); }
   BlockDesc* desc() const { return (BlockDesc*)(work + L.desc); }
-  bool mixed() const { return o.precision == IBMI_PREC_FP32_UPDATE; }
+  bool mixed() const { return o.precision != IBMI_PREC_FP64; }
+  // bfloat16 terms per operand of the update product (0: plain FP32 products)
+  int split_terms() const {
+    return o.precision == IBMI_PREC_BF16X3_UPDATE ? 2
+           : o.precision == IBMI_PREC_BF16X6_UPDATE ? 3 : 0;
+  }
+  float* spart() const { return (float*)(work + L.spart); }
   float* a32() const { return (float*)(work + L.a32); }
   float* dmat() const { return (float*)(work + L.dmat); }
   double* rt() const { return (double*)(work + L.rt); }
@@ -429,7 +455,7 @@ ibmi_status ibmi_plan(ibmi_plan_t* out, const ibmi_options* opts, const double* 
         return fail(IBMI_ERR_HIP);
     }
   }
-  if (P->mixed() && ibmi::to_f32(P->A, P->lda, P->a32(), P->p, st) != hipSuccess)
+  if (P->mixed() && ibmi::to_f32(P->A, P->lda, P->a32(), P->L.ld32, P->p, st) != hipSuccess)
     return fail(IBMI_ERR_HIP);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(IBMI_ERR_HIP);
   *out = P;
@@ -517,16 +543,24 @@ static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int 
   }
   const IdxMap g{0, s, b};
   hipEvent_t ev = prof_begin(P, 0);
-  Opnd Xa32{(const double*)P->a32(), p, IdxMap{}, IdxMap{s, INT64_MAX, 0}};
-  Opnd Yd32{(const double*)P->dmat(), p, IdxMap{}, IdxMap{}};
-  IBMI_HIP(ibmi::gemm_f32_subfrom(P->t.upd32, Xa32, Yd32, b, p, p, u, u, P->rt(), p, s, P->rkt(),
-                                  p, st));
+  const int64_t ld32 = P->L.ld32;
+  if (const int terms = P->split_terms()) {
+    // A and D are symmetric: rows s.. of A and the rows of D are the operands.
+    IBMI_HIP(ibmi::gemm_split_subfrom(P->t.split, terms, P->a32(), ld32, s, P->dmat(), ld32, b,
+                                      p, p, u, u, P->t.split_kchunk, P->rt(), p, s, P->rkt(), p,
+                                      P->spart(), st));
+  } else {
+    Opnd Xa32{(const double*)P->a32(), ld32, IdxMap{}, IdxMap{s, INT64_MAX, 0}};
+    Opnd Yd32{(const double*)P->dmat(), ld32, IdxMap{}, IdxMap{}};
+    IBMI_HIP(ibmi::gemm_f32_subfrom(P->t.upd32, Xa32, Yd32, b, p, p, u, u, P->rt(), p, s,
+                                    P->rkt(), p, st));
+  }
   prof_end(P, 0, ev, 2.0 * (double)b * ((double)u * p + (double)(p - u) * u));
   ev = prof_begin(P, 1);
   Opnd Xr{P->rkt(), p, IdxMap{}, g};
   Opnd Yi{P->ainv(k), b, IdxMap{}, IdxMap{}};
-  IBMI_HIP(ibmi::gemm_corr(P->t.plan, Xr, Yi, c, b, b, P->delta(), b, dH, ldh, P->dmat(), p, s, g,
-                           st));
+  IBMI_HIP(ibmi::gemm_corr(P->t.plan, Xr, Yi, c, b, b, P->delta(), b, dH, ldh, P->dmat(), ld32, s,
+                           g, st));
   const int splits = diag_splits_for(b, c, P->t.diag, P->t.diag_splits);
   Opnd Xd{P->delta(), b, IdxMap{}, IdxMap{}};
   Opnd Ya{P->A, P->lda, g, IdxMap{s, INT64_MAX, 0}};
@@ -534,7 +568,7 @@ static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int 
   IBMI_HIP(ibmi::corr_diag(P->rkt(), p, s, P->part(), splits, b, P->tt(), st));
   Opnd Xt{P->tt(), b, IdxMap{}, IdxMap{}};
   IBMI_HIP(ibmi::gemm_store(P->t.small, Xt, Yi, b, b, b, P->x2(), b, st));
-  IBMI_HIP(ibmi::corr_apply(P->x2(), b, dH, ldh, P->dmat(), p, s, st));
+  IBMI_HIP(ibmi::corr_apply(P->x2(), b, dH, ldh, P->dmat(), ld32, s, st));
   prof_end(P, 1, ev, 4.0 * (double)b * b * c + 2.0 * (double)b * b * b);
   return IBMI_OK;
 }
@@ -549,7 +583,8 @@ static ibmi_status sweep_once(ibmi_plan_t P, double* dH, int64_t ldh, bool resta
       ibmi_status rc = block_step(P, dH, ldh, k);
       if (rc != IBMI_OK) return rc;
     }
-    return residual_sq(P, dH, ldh, want_h, res_sq, h_sq, nullptr);
+    return residual_sq(P, dH, ldh, want_h, res_sq, h_sq,
+                       P->o.stop == IBMI_STOP_REL_HR ? P->rt() : nullptr);
   }
   const int64_t p = P->p;
   if (restart) {
@@ -557,7 +592,7 @@ static ibmi_status sweep_once(ibmi_plan_t P, double* dH, int64_t ldh, bool resta
     ibmi_status rc = residual_sq(P, dH, ldh, false, &ignore, nullptr, P->rt());
     if (rc != IBMI_OK) return rc;
   }
-  IBMI_HIP(ibmi::zero_f32(P->dmat(), p * p, P->st));
+  IBMI_HIP(ibmi::zero_f32(P->dmat(), p * P->L.ld32, P->st));
   int64_t u = 0;
   for (int k = 0; k < K; ++k) {
     ibmi_status rc = block_step_mixed(P, dH, ldh, k, u);
@@ -626,6 +661,20 @@ static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, boo
   return IBMI_OK;
 }
 
+// ||H R||_F^2 with R = I - A H as stored by the last residual evaluation (H symmetric, so
+// the product's row operand H^T is H itself).
+static ibmi_status hr_sq(ibmi_plan_t P, const double* dH, int64_t ldh, double* out) {
+  hipStream_t st = P->st;
+  Opnd Xh{dH, ldh, IdxMap{}, IdxMap{}};
+  Opnd Yr{P->rt(), P->p, IdxMap{}, IdxMap{}};
+  int64_t n_red = 0;
+  IBMI_HIP(ibmi::gemm_sumsq(P->t.resid, Xh, Yr, P->p, P->p, P->p, P->red(), &n_red, st));
+  IBMI_HIP(ibmi::reduce_sum(P->red(), n_red, P->scal() + 2, st));
+  IBMI_HIP(hipMemcpyAsync(out, P->scal() + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  IBMI_HIP(hipStreamSynchronize(st));
+  return IBMI_OK;
+}
+
 ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, double* out) {
   ibmi_status rc = check_h(plan, dH, ldh);
   if (rc != IBMI_OK) return rc;
@@ -647,9 +696,10 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
   rc = ibmi_init_h(plan, dH, ldh);
   if (rc != IBMI_OK) return rc;
   const int limit = o.fixed_sweeps > 0 ? o.fixed_sweeps : o.max_sweeps;
-  const bool want_h = o.stop == IBMI_STOP_REL_BOUND;
+  const bool want_h = o.stop != IBMI_STOP_FRO;
   double best = INFINITY;
   int since_best = 0;
+  double ratio = -1.0, rho_eval = 0.0;  // REL_HR: last bound / ||R||_F, and that ||R||_F
   while (true) {
     double r2 = 0.0, h2 = 0.0;
     rc = sweep_once(plan, dH, ldh, info->sweeps == 0, want_h, &r2, &h2);
@@ -659,7 +709,28 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
     info->residual = rho;
     if (!std::isfinite(rho)) return IBMI_ERR_NONFINITE;
     if (history) history[info->sweeps - 1] = rho;
-    const double sv = want_h ? rho / (o.lambda_min * std::sqrt(h2)) : rho;
+    double sv = rho;
+    if (o.stop == IBMI_STOP_REL_BOUND) {
+      sv = rho / (o.lambda_min * std::sqrt(h2));
+    } else if (o.stop == IBMI_STOP_REL_HR) {
+      const bool last = o.fixed_sweeps > 0 && info->sweeps >= limit;
+      const bool due = rho < 1.0 && (ratio < 0.0 || ratio * rho < o.tol || rho < 0.1 * rho_eval);
+      if (due || last) {
+        sv = INFINITY;
+        if (rho < 1.0) {
+          double hr2 = 0.0;
+          rc = hr_sq(plan, dH, ldh, &hr2);
+          if (rc != IBMI_OK) return rc;
+          const double x = std::sqrt(hr2) / ((1.0 - rho) * std::sqrt(h2));
+          if (x < 1.0) sv = x / (1.0 - x);
+        }
+        ratio = rho > 0.0 ? sv / rho : 0.0;
+        rho_eval = rho;
+        info->evaluations += 1;
+      } else {
+        sv = ratio >= 0.0 ? ratio * rho : INFINITY;
+      }
+    }
     info->stop_value = sv;
     // Stagnation guard, in the units of the stop test.
     if (sv < 0.99 * best) {

@@ -41,7 +41,8 @@ enum {
   EPI_RESID = 3,        // red[slot] = sum over the tile of (delta_mn - C)^2
   EPI_RESID_STORE = 4,  // out[m][n] = delta_mn - C and red[slot] = sum of its squares
   EPI_SUBFROM = 5,      // out[m][n] = src[(s+m)][n] - C
-  EPI_CORR = 6          // correction of H[I^c,I] and D (FP32-update form)
+  EPI_CORR = 6,         // correction of H[I^c,I] and D (FP32-update form)
+  EPI_SUMSQ = 7         // red[slot] = sum over the tile of C^2
 };
 
 struct EpiArgs {
@@ -123,6 +124,9 @@ hipError_t gemm_partial(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64
 // count to *n_red; when out is non-null also stores delta_mn - C to out[m * ldo + n].
 hipError_t gemm_resid(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
                       double* red, int64_t* n_red, double* out, int64_t ldo, hipStream_t st);
+// Writes one partial sum of C[m][n]^2 per tile to red (gemm_tiles of them), count to *n_red.
+hipError_t gemm_sumsq(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, double* red,
+                      int64_t* n_red, hipStream_t st);
 // FP32 operands, FP32 accumulation: out[m][n] = src[(s+m)*lds + n] - C[m][n].  Column tiles
 // starting at n0 >= ncut only sum k < klim (the rest of the operand is known to be zero).
 hipError_t gemm_f32_subfrom(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
@@ -133,7 +137,34 @@ hipError_t gemm_f32_subfrom(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, i
 hipError_t gemm_corr(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
                      double* delta, int64_t ld_delta, double* H, int64_t ldh, float* D,
                      int64_t ldd, int64_t s, IdxMap g, hipStream_t st);
-hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t p, hipStream_t st);
+// Split-bfloat16 form of the same update (terms = 2: bf16x3, terms = 3: bf16x6):
+// out[m][n] = src[(s+m)*lds + n] - sum_k X[(xrow0+m)*ldx + k] * Y[n*ldy + k] for m < M,
+// n < N, k < K (k < klim for column tiles starting at or after ncut).  K is cut into chunks
+// of kchunk (0: one chunk); with more than one chunk per tile the FP32 partial products go to
+// part (split_max_chunks(K, kchunk) * M * N floats) and a second kernel sums them in order.
+// X, Y 16-byte aligned, ldx and ldy multiples of 4.
+enum SplitCfg {
+  SPLIT_128x128 = 0,  // 2x2 waves of 64x64
+  SPLIT_64x128 = 1,   // 1x2 waves of 64x64
+  SPLIT_96x128 = 2,   // 2x2 waves of 48x64
+  SPLIT_192x128 = 3,  // 3x2 waves of 64x64
+  SPLIT_144x128 = 4,  // 3x2 waves of 48x64
+  SPLIT_64x64 = 5,    // 1 wave of 64x64
+  SPLIT_CFG_COUNT = 6
+};
+struct SplitDims {
+  int bm, bn, bk;
+};
+SplitDims split_dims(SplitCfg c);
+int64_t split_max_chunks(int64_t K, int64_t kchunk);
+hipError_t gemm_split_subfrom(SplitCfg cfg, int terms, const float* X, int64_t ldx,
+                              int64_t xrow0, const float* Y, int64_t ldy, int64_t M, int64_t N,
+                              int64_t K, int64_t ncut, int64_t klim, int64_t kchunk,
+                              const double* src, int64_t lds, int64_t s, double* out,
+                              int64_t ldo, float* part, hipStream_t st);
+// out (p x ldo) = FP32 copy of A (p x p, row stride lda).
+hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t ldo, int64_t p,
+                  hipStream_t st);
 hipError_t zero_f32(float* x, int64_t n, hipStream_t st);
 hipError_t corr_diag(const double* rkt, int64_t ldr, int64_t s, const double* part, int splits,
                      int64_t b, double* tt, hipStream_t st);

@@ -300,17 +300,18 @@ hipError_t reduce_sum(const double* red, int64_t n, double* out, hipStream_t st)
 // ---------------------------------------------------------------------------------------
 // Mixed (FP32-update) form helpers.
 // ---------------------------------------------------------------------------------------
-__global__ void to_f32_kernel(const double* a, int64_t lda, float* out, int64_t p) {
-  const int64_t n = p * p;
+__global__ void to_f32_kernel(const double* a, int64_t lda, float* out, int64_t ldo, int64_t p) {
+  const int64_t n = p * ldo;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / p, j = e % p;
-    out[e] = (float)a[i * lda + j];
+    const int64_t i = e / ldo, j = e % ldo;
+    out[e] = j < p ? (float)a[i * lda + j] : 0.0f;
   }
 }
 
-hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t p, hipStream_t st) {
-  hipLaunchKernelGGL(to_f32_kernel, dim3(8192), dim3(256), 0, st, a, lda, out, p);
+hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t ldo, int64_t p,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(8192), dim3(256), 0, st, a, lda, out, ldo, p);
   return hipGetLastError();
 }
 

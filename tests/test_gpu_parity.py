@@ -213,27 +213,35 @@ def test_full_size_16384_first_block_and_properties(ib):
     plan.close()
 
 
-# ------------------------------------------------------------------ FP32-update form
+# ------------------------------------------------------------ low-precision update forms
 
-def test_mixed_form_refines_to_fp64_oracle(ib):
-    """FP32 matrix-core products in the correction form, FP64 factors and residual: the
-    converged H matches the FP64 oracle's converged H to the FP64 bar."""
-    _say("mixed form p=2048 Matern-3/2 to rel bound 1e-10")
+MIXED = ["fp32", "bf16x3", "bf16x6"]
+# Unit roundoff of the update product: FP32, a two-term bfloat16 split (16 significant bits,
+# the dropped lo*lo term is of the same order), a three-term split (about FP32's).
+U_LOW = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16, "bf16x6": 2.0 ** -23}
+
+
+@pytest.mark.parametrize("form", MIXED)
+def test_mixed_form_refines_to_fp64_oracle(ib, form):
+    """Low-precision matrix-core products in the correction form, FP64 factors and residual:
+    the converged H matches the FP64 oracle's converged H to the FP64 bar."""
+    _say(f"{form} form p=2048 Matern-3/2 to rel bound 1e-10")
     A = workloads.config2_matrix(p=2048)
     ranges = oracle.partition(2048, 576, 64)
     ref = oracle.ibmi_solve(A, ranges, tol=1e-10, stop="rel_bound", lam_min=1e-2, max_sweeps=500)
     assert ref.converged
-    out, H = _gpu_solve(ib, A, block_rows=576, overlap=64, precision="fp32", stop="rel_bound",
+    out, H = _gpu_solve(ib, A, block_rows=576, overlap=64, precision=form, stop="rel_bound",
                         lambda_min=1e-2, tol=1e-10, max_sweeps=500)
     assert out.converged and np.array_equal(H, H.T)
-    assert abs(out.sweeps - ref.sweeps) <= 2
+    assert abs(out.sweeps - ref.sweeps) <= (2 if form != "bf16x3" else 4)
     assert _rel(H, ref.h) <= TOL
 
 
-def test_mixed_form_ragged_against_inverse(ib):
-    _say("mixed form ragged wishart p=1000 b=256 ovl=40")
+@pytest.mark.parametrize("form", MIXED)
+def test_mixed_form_ragged_against_inverse(ib, form):
+    _say(f"{form} form ragged wishart p=1000 b=256 ovl=40")
     A = workloads.wishart_spd(1000, np.random.default_rng(3), shift=0.3)
-    out, H = _gpu_solve(ib, A, block_rows=256, overlap=40, precision="fp32", stop="rel_bound",
+    out, H = _gpu_solve(ib, A, block_rows=256, overlap=40, precision=form, stop="rel_bound",
                         lambda_min=0.3, tol=1e-12, max_sweeps=500)
     assert out.converged
     assert _rel(H, np.linalg.inv(A)) <= TOL
@@ -242,22 +250,70 @@ def test_mixed_form_ragged_against_inverse(ib):
     assert _rel(H, ref.h) <= TOL
 
 
-def test_mixed_first_sweep_close_to_fp64(ib):
-    """One mixed sweep differs from the FP64 sweep only by FP32 rounding of D A[:,I]; in the
-    first sweep D is bounded by |H|, so the difference is a small multiple of u_fp32 * kappa."""
-    _say("mixed vs fp64 single sweep p=777")
+@pytest.mark.parametrize("form", MIXED)
+def test_mixed_first_sweeps_close_to_fp64(ib, form):
+    """Two low-precision sweeps differ from the FP64 sweeps only by the rounding of the
+    product D A[:,I]; D is bounded by |H| there, so the difference is a small multiple of
+    u_low * kappa.  p = 777 leaves a ragged row stride for the FP32 copies."""
+    _say(f"{form} vs fp64 two sweeps p=777")
     A = workloads.wishart_spd(777, np.random.default_rng(6), shift=0.5)
     ranges = oracle.partition(777, 200, 24)
     ref = oracle.ibmi_solve(A, ranges, tol=1e-300, fixed_sweeps=2)
-    out, H = _gpu_solve(ib, A, bounds=ranges, precision="fp32", tol=1e-300, fixed_sweeps=2)
+    out, H = _gpu_solve(ib, A, bounds=ranges, precision=form, tol=1e-300, fixed_sweeps=2)
     kappa = np.linalg.cond(A)
-    assert _rel(H, ref.h) < 100 * np.finfo(np.float32).eps * kappa
+    assert _rel(H, ref.h) < 100 * U_LOW[form] * kappa
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6"])
+def test_split_products_match_emulation(ib, form):
+    """The matrix-core split-bfloat16 product is the oracle's emulated one (same terms, same
+    dropped pairs, round to nearest even) up to FP32 accumulation order.  Measured on the CPU
+    for this case (bf16x3): emulation vs FP64 1.2e-5, two FP32 accumulation orders 3.2e-6,
+    truncating instead of rounding 3.9e-5 away, keeping only hi*hi 6.7e-2 away.  So the GPU
+    H must sit nearer the emulation than half the emulation's distance from FP64.  For
+    bf16x6 the split error is at the accumulation-order level (4e-7), so only a lost or
+    extra term (1.2e-5 for the bf16x3 pairs) is detectable: within 3x of that distance."""
+    _say(f"{form} vs emulated {form} two sweeps p=900")
+    A = workloads.config2_matrix(p=900)
+    ranges = oracle.partition(900, 256, 32)
+    bp = oracle.plan(A, ranges)
+    h_emul, h64 = np.eye(900), np.eye(900)
+    for _ in range(2):
+        oracle.correction_sweep(A, h_emul, bp, form)
+        oracle.correction_sweep(A, h64, bp, "fp64")
+    out, H = _gpu_solve(ib, A, bounds=ranges, precision=form, tol=1e-300, fixed_sweeps=2)
+    gap_low = _rel(h_emul, h64)
+    assert gap_low > 0
+    limit = 0.5 if form == "bf16x3" else 3.0
+    assert _rel(H, h_emul) < limit * gap_low, (_rel(H, h_emul), gap_low)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3"])
+def test_rel_hr_stop_matches_oracle(ib, form):
+    """The H R relative-error stop: same stopping sweep as the oracle (FP64 form: same
+    evaluations too, and the same H to the FP64 bar), and the returned H is within tol of
+    LAPACK's inverse."""
+    _say(f"rel_hr stop, {form} form, p=1200 Matern-3/2, tol 1e-9")
+    A = workloads.config2_matrix(p=1200)
+    ranges = oracle.partition(1200, 300, 40)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-9, stop="rel_hr", max_sweeps=300)
+    assert ref.converged
+    out, H = _gpu_solve(ib, A, bounds=ranges, precision=form, tol=1e-9, stop="rel_hr",
+                        max_sweeps=300)
+    assert out.converged and out.stop_value < 1e-9
+    assert _rel(H, np.linalg.inv(A)) < 1e-9
+    if form == "fp64":
+        assert out.sweeps == ref.sweeps and out.evaluations == ref.evaluations
+        assert out.stop_value == pytest.approx(ref.stop_value, rel=0.02)  # R rounding noise
+        assert _rel(H, ref.h) <= TOL
+    else:
+        assert abs(out.sweeps - ref.sweeps) <= 2
 
 
 def test_sweep_entry_point_matches_solve(ib):
     _say("ibmi_sweep vs ibmi_solve p=640")
     A = workloads.config2_matrix(p=640)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         plan = ib.Plan(_dev(A), block_rows=200, overlap=24, precision=prec, fixed_sweeps=3,
                        tol=1e-300)
         h_solve = plan.solve().H.clone()

@@ -407,3 +407,55 @@ def test_stagnation_guard_works_in_the_stop_test_units():
     bound = res.history[-1] / (1e-2 * np.linalg.norm(res.h))
     assert res.floor_limited and not res.converged and res.sweeps < 40
     assert 1e-12 < bound < 100 * 1e-12
+
+
+def test_hr_bound_closed_form_scaled_inverse():
+    """H = (1 - d) A^{-1} for diagonal A: R = d I, H R = d (1 - d) A^{-1}, so the bound is
+    x / (1 - x) with x = d / (1 - d sqrt(p)), and the true relative error is d <= bound."""
+    p, d = 50, 1e-3
+    A = np.diag(np.arange(1.0, p + 1.0))
+    H = (1.0 - d) * np.diag(1.0 / np.arange(1.0, p + 1.0))
+    bound, rho = oracle.hr_error_bound(A, H)
+    x = d / (1.0 - d * np.sqrt(p))
+    assert rho == pytest.approx(d * np.sqrt(p), rel=1e-12)
+    assert bound == pytest.approx(x / (1.0 - x), rel=1e-10)
+    assert bound >= d
+    assert oracle.hr_error_bound(A, 0.5 * np.linalg.inv(A))[0] == float("inf")  # ||R||_F >= 1
+
+
+def test_hr_bound_is_certified_and_tight_along_iteration():
+    """Along an IBMI iteration the bound is never below the true relative error (computed
+    from LAPACK's inverse) and is tight to first order in ||R||_F: once ||R||_F < 0.1 it
+    exceeds the true error by less than a factor 1 + 1.5 ||R||_F."""
+    A = workloads.wishart_spd(400, np.random.default_rng(11), shift=0.05)
+    ranges = oracle.partition(400, 120, 16)
+    P = oracle.plan(A, ranges)
+    H = np.eye(400)
+    inv = np.linalg.inv(A)
+    seen = 0
+    for r in range(40):
+        oracle.sweep(H, P)
+        bound, rho = oracle.hr_error_bound(A, H)
+        true = _rel(H, inv)
+        if np.isfinite(bound):
+            assert bound >= true * (1 - 1e-9)
+            if rho < 0.1:
+                assert bound <= (1.0 + 1.5 * rho) * true
+                seen += 1
+    assert seen >= 5
+
+
+def test_rel_hr_stop_ends_at_the_true_error():
+    """The rel_hr stop converges once the certified bound is below tol, evaluating the
+    bound at a few sweeps only; the true error of the returned H is below tol while one
+    sweep earlier it was not."""
+    A = workloads.config2_matrix(p=1200)
+    ranges = oracle.partition(1200, 300, 40)
+    tol = 1e-9
+    res = oracle.ibmi_solve(A, ranges, tol=tol, stop="rel_hr", max_sweeps=300)
+    inv = np.linalg.inv(A)
+    assert res.converged and res.stop_value < tol
+    assert _rel(res.h, inv) < tol
+    assert 1 <= res.evaluations <= 10 and res.evaluations < res.sweeps
+    prev = oracle.ibmi_solve(A, ranges, tol=1e-300, fixed_sweeps=res.sweeps - 1)
+    assert _rel(prev.h, inv) > 0.5 * tol
