@@ -289,8 +289,24 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   X_(GEMM_96x128, 96, 128, 32, 2, 2)                                                           \
   X_(GEMM_192x96, 192, 96, 16, 2, 2)
 
+// Waves per SIMD that the LDS of one workgroup allows (160 KiB per CU, 4 SIMDs), capped at 8.
+// The 8-wave tiles of the residual epilogues that store or square the product ask the
+// compiler for at least this occupancy: left alone it spends a few registers more than that
+// occupancy leaves and loses a wave per SIMD (measured: 57.7 against 65.8 TFLOP/s for the
+// stored residual at p = 16384).
+template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI>
+constexpr int gemm_min_waves() {
+  if ((EPI != EPI_RESID_STORE && EPI != EPI_SUMSQ) || WM * WN != 8) return 1;
+  constexpr int pad = sizeof(T) == 4 ? 16 : 0;
+  constexpr int lds = 2 * BK * (BM + BN + 2 * pad) * (int)sizeof(T) + 64;
+  constexpr int wgs = (160 * 1024) / lds;
+  constexpr int w = wgs * WM * WN / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ>
 __global__ void __launch_bounds__(64 * WM * WN)
+__attribute__((amdgpu_waves_per_eu(gemm_min_waves<T, BM, BN, BK, WM, WN, EPI>())))
 gemm_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int64_t kchunk, int mtc, int ntc,
             int per_xcd, int gm, EpiArgs ea) {
   const int bx = blockIdx.x;

@@ -124,15 +124,17 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
 // Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel and
 // diagonal products favour small tiles with many resident waves, the square residual the
 // 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 96x128 tiles
-// with K cut into chunks of 4096 (six row tiles of a 576-row set times four chunks fill the
-// chip where whole-K tiles leave it half idle).
+// (two terms) or 6-wave 192x128 tiles (three terms) with K cut into chunks of 2048 (the few
+// row tiles of a 576-row set times eight chunks fill the chip where whole-K tiles leave it
+// half idle).
 struct Tuning {
   GemmCfg panel = ibmi::GEMM_64x64_K16, diag = ibmi::GEMM_64x64_K16,
           resid = ibmi::GEMM_128x128_W8, plan = ibmi::GEMM_64x64_K16, upd32 = ibmi::GEMM_64x64,
           small = ibmi::GEMM_64x64_K16;
   int diag_splits = 0;  // 0 = automatic
-  SplitCfg split = ibmi::SPLIT_96x128;  // split-bfloat16 update product
-  int64_t split_kchunk = 4096;          // its K chunk (0: whole K per tile)
+  SplitCfg split = ibmi::SPLIT_96x128;   // split-bfloat16 update product, two terms
+  SplitCfg split6 = ibmi::SPLIT_192x128; // the same with three terms
+  int64_t split_kchunk = 2048;           // their K chunk (0: whole K per tile)
 };
 
 Tuning tuning_for(int64_t p) {
@@ -148,7 +150,7 @@ Tuning tuning_for(int64_t p) {
   if (const char* v = std::getenv("IBMI_DIAG_SPLITS")) t.diag_splits = std::max(1, std::atoi(v));
   if (const char* v = std::getenv("IBMI_CFG_SPLIT")) {
     const int i = std::atoi(v);
-    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = (SplitCfg)i;
+    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = t.split6 = (SplitCfg)i;
   }
   if (const char* v = std::getenv("IBMI_SPLIT_KCHUNK")) t.split_kchunk = std::max(0, std::atoi(v));
   return t;
@@ -546,7 +548,8 @@ static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int 
   const int64_t ld32 = P->L.ld32;
   if (const int terms = P->split_terms()) {
     // A and D are symmetric: rows s.. of A and the rows of D are the operands.
-    IBMI_HIP(ibmi::gemm_split_subfrom(P->t.split, terms, P->a32(), ld32, s, P->dmat(), ld32, b,
+    IBMI_HIP(ibmi::gemm_split_subfrom(terms == 2 ? P->t.split : P->t.split6, terms, P->a32(),
+                                      ld32, s, P->dmat(), ld32, b,
                                       p, p, u, u, P->t.split_kchunk, P->rt(), p, s, P->rkt(), p,
                                       P->spart(), st));
   } else {
