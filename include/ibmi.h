@@ -95,8 +95,8 @@ typedef struct {
   double lambda_min;       /* > 0 when stop = REL_BOUND                                    */
   int32_t max_sweeps;      /* >= 1; hitting it is not an error (converged = 0)             */
   int32_t stagnation_guard;/* 1: stop (floor_limited = 1) once the best stop value (the     */
-                           /*    quantity compared with tol) is below 100 tol and 4 sweeps */
-                           /*    in a row failed to improve it by 1%                       */
+                           /*    quantity compared with tol) is below 100 tol and 16      */
+                           /*    sweeps in a row failed to improve it by 1%                */
   int32_t fixed_sweeps;    /* > 0: run exactly this many sweeps, ignore tol and the guard  */
   int32_t reserved;
 } ibmi_options;

@@ -212,6 +212,9 @@ def _stop_value(a, h, rho, stop, lam_min):
     raise IbmiError("INVALID_ARG", f"unknown stop test {stop!r}")
 
 
+GUARD_SWEEPS = 16  # sweeps without a 1% improvement that end a solve at its floor
+
+
 def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
                max_sweeps: int = 500, stagnation_guard: bool = True, stop: str = "fro",
                lam_min: float = 0.0, fixed_sweeps: int = 0) -> SolveResult:
@@ -228,8 +231,9 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     least one sweep, and returns H after ``max_sweeps`` with converged=False when the test
     never passes.  Stagnation guard (the FP64 floor of ||I - A H||_F can lie above tol):
     stop with floor_limited=True once the best stop value so far (the quantity compared with
-    tol) is below 100 tol and no sweep has improved on it by at least 1% for four sweeps in a
-    row.
+    tol) is below 100 tol and no sweep has improved on it by at least 1% for sixteen sweeps
+    in a row (a window long enough that the sweep-to-sweep noise of a slowly converging
+    iteration, about 1% per sweep at p = 16384, does not end it early).
     ``fixed_sweeps > 0`` runs exactly that many sweeps (parity at equal sweep counts).
     """
     if tol <= 0 or max_sweeps < 1:
@@ -273,7 +277,7 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
             break
         if res.sweeps >= limit:
             break
-        if stagnation_guard and best < 100.0 * tol and since_best >= 4:
+        if stagnation_guard and best < 100.0 * tol and since_best >= GUARD_SWEEPS:
             res.floor_limited = True
             break
     return res

@@ -759,7 +759,7 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
       break;
     }
     if (info->sweeps >= limit) break;
-    if (o.stagnation_guard && best < 100.0 * o.tol && since_best >= 4) {
+    if (o.stagnation_guard && best < 100.0 * o.tol && since_best >= ibmi::kGuardSweeps) {
       info->floor_limited = 1;
       break;
     }

@@ -79,6 +79,11 @@ struct FinTask {
   int32_t splits, mat;
 };
 
+// Stagnation guard: sweeps in a row without a 1% improvement of the best stop value that
+// end a solve at its floor (long enough that the sweep-to-sweep noise of a slowly converging
+// iteration does not end it early).
+constexpr int kGuardSweeps = 16;
+
 // Per-matrix state of a batched solve.
 struct BatchState {
   int32_t sweeps, converged, floor_limited, since_best;

@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(256) batch_check_kernel(const double* red, con
         } else {
           s.since_best += 1;
         }
-        if (guard && s.best < 100.0 * tol && s.since_best >= 4) {
+        if (guard && s.best < 100.0 * tol && s.since_best >= kGuardSweeps) {
           s.floor_limited = 1;
           stop = true;
         }

@@ -391,7 +391,7 @@ def test_stagnation_guard_stops_at_the_floor():
     res = oracle.ibmi_solve(A, ranges, tol=1e-11, max_sweeps=500)  # floor here: 2.9e-10
     assert res.floor_limited and not res.converged and res.sweeps < 30
     best = min(res.history)
-    assert best < 100 * 1e-11 and all(h > 0.99 * best for h in res.history[-4:])
+    assert best < 100 * 1e-11 and all(h > 0.99 * best for h in res.history[-16:])
     res2 = oracle.ibmi_solve(A, ranges, tol=1e-8, max_sweeps=500)
     assert res2.converged and not res2.floor_limited
 
