@@ -16,9 +16,13 @@ LIB = os.path.join(HERE, "libibmi.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["kernels.hip", "gemm_f64_a.hip", "gemm_f64_b.hip", "gemm_f32.hip", "gemm_grouped.hip",
            "gemm_split.hip", "ibmi.cpp", "batch.cpp"]
-# Packed FP32 instructions are disabled on purpose for every device pass.
+# Packed FP32 instructions are disabled on purpose for every device pass.  Matrix-core
+# instructions take their accumulators in ordinary vector registers: with the default
+# (accumulation registers) the compiler copies every accumulator out and back once per K
+# stage of the GEMM loops.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1",
             "-Wno-unused-result"]
 
 

@@ -68,6 +68,23 @@ template <> struct Mfma<float> {
 // tiles go in groups of `gm` M-tiles per N column so the workgroups resident on one XCD share
 // operand panels in that XCD's L2.
 // ---------------------------------------------------------------------------------------
+// LDS of one tile configuration.  Declared in a function that does not depend on the
+// epilogue, so a kernel that runs the same tile code with two epilogues (stream-K panel) holds
+// one copy.  FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction;
+// padding each row by 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left
+// unpadded (no bank conflicts measured).
+template <typename T, int BM, int BN, int BK, int NW>
+struct GemmSmem {
+  static constexpr int PAD = sizeof(T) == 4 ? 16 : 0;
+  T Xs[2][BK][BM + PAD];
+  T Ys[2][BK][BN + PAD];
+};
+template <typename T, int BM, int BN, int BK, int NW>
+__device__ __forceinline__ GemmSmem<T, BM, BN, BK, NW>& gemm_smem() {
+  __shared__ __attribute__((aligned(16))) GemmSmem<T, BM, BN, BK, NW> sm;
+  return sm;
+}
+
 // VEC-wide loads need every thread to own a multiple of VEC elements of each operand tile.
 template <int XE, int YE, int VEC>
 struct VecWidth {
@@ -77,8 +94,12 @@ struct VecWidth {
 
 // Work of one output tile: rows [mt*BM, ..) and columns [nt*BN, ..) of C, summed over k in
 // [kb, ke), which is K chunk `z` of a split-K product; `slot` is where the residual
-// epilogues put this tile's partial sum.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ>
+// epilogues put this tile's partial sum.  FULL: the caller guarantees that the tile lies
+// inside M x N and that ke - kb is a multiple of BK (with VEC-wide loads valid), so the
+// K loop has no branches: that keeps the accumulators in the matrix-core registers across
+// iterations (with a branch in the loop the compiler copies all of them out and back every
+// stage).
+template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ, bool FULL = false>
 __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t M, int64_t N,
                                           int64_t kb, int64_t ke, int mt, int nt, int z,
                                           int64_t slot, const EpiArgs& ea) {
@@ -95,12 +116,14 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   static_assert(XV * VEC == XE && YV * VEC == YE && BM % VEC == 0 && BN % VEC == 0, "bad VEC");
   static_assert(TM * 16 == WTM && TN * 16 == WTN && BK % 4 == 0, "bad wave tile");
 
-  // FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction; padding each
-  // row by 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left unpadded.
-  constexpr int PAD = sizeof(T) == 4 ? 16 : 0;
-  __shared__ __attribute__((aligned(16))) T Xs[2][BK][BM + PAD];
-  __shared__ __attribute__((aligned(16))) T Ys[2][BK][BN + PAD];
-  __shared__ double red_s[NT / 64];
+  auto& sm = gemm_smem<T, BM, BN, BK, NT / 64>();
+  auto& Xs = sm.Xs;
+  auto& Ys = sm.Ys;
+  // The per-wave partial sums of the residual epilogues reuse the operand buffers: they are
+  // written after the loop's last barrier, when no wave reads the operands any more.  (A
+  // separate array would push the 64x64x16 tile's LDS just past a fifth of the CU's.)
+  double* red_s = reinterpret_cast<double*>(&sm.Xs[0][0][0]);
+  static_assert(sizeof(sm.Xs) >= (NT / 64) * sizeof(double), "no room for the wave sums");
 
   const int tid = threadIdx.x;
   const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
@@ -117,7 +140,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   // offset (its row within the stage times ld, plus its mapped column), bumped by skip*ld
   // for rows past the map's cut.  Edge tiles and a ragged last K stage take the
   // bounds-checked scalar path.  The choice is uniform over the workgroup.
-  const bool interior = VEC > 1 && m0 + BM <= M && n0 + BN <= N;
+  const bool interior = FULL || (VEC > 1 && m0 + BM <= M && n0 + BN <= N);
   int xkk[XV], xoff[XV], ykk[YV], yoff[YV];
 #pragma unroll
   for (int v = 0; v < XV; ++v) {
@@ -136,7 +159,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   T xr[XE], yr[YE];
   auto gload = [&](int kt) {
     const int64_t k0 = kb + (int64_t)kt * BK;
-    if (interior && k0 + BK <= ke) {
+    if (FULL || (interior && k0 + BK <= ke)) {
       const T* xb = xp + (X.r.base + k0) * X.ld;
       const T* yb = yp + (Y.r.base + k0) * Y.ld;
       const int xcut = (int)mn64(mx64(X.r.cut - k0, -1), BK + 1);
@@ -195,14 +218,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  if (nk > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[TM], b[TN];
@@ -215,7 +231,23 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  // Stages 0 .. nk-2 prefetch the next stage into registers while the matrix cores work on
+  // the current one; the last stage is peeled so the loop body has no conditions.
+  for (int kt = 0; kt + 1 < nk; ++kt) {
+    gload(kt + 1);
+    compute(kt & 1);
+    sstore((kt + 1) & 1);
+    __syncthreads();
+  }
+  if (nk > 0) {
+    compute((nk - 1) & 1);
     __syncthreads();
   }
 
@@ -247,6 +279,14 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
           ss += d * d;
         } else if constexpr (EPI == EPI_SUMSQ) {
           ss += v * v;
+        } else if constexpr (EPI == EPI_PANEL_SK) {
+          if (z >= 0) {  // a piece of a shared tile: tile-local partial slot z
+            ea.red[(int64_t)z * (BM * BN) + (m - m0) * BN + (n - n0)] = v;
+          } else {
+            const int64_t gn = ea.g(n);
+            ea.out[(ea.s + m) * ea.ldo + gn] = -v;
+            ea.out[gn * ea.ldo + ea.s + m] = -v;
+          }
         } else if constexpr (EPI == EPI_SUBFROM) {
           ea.out[m * ea.ldo + n] = ea.src[(ea.s + m) * ea.lds + n] - v;
         } else {
@@ -294,17 +334,21 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
 // compiler for at least this occupancy: left alone it spends a few registers more than that
 // occupancy leaves and loses a wave per SIMD (measured: 57.7 against 65.8 TFLOP/s for the
 // stored residual at p = 16384).
-template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI>
-constexpr int gemm_min_waves() {
-  if ((EPI != EPI_RESID_STORE && EPI != EPI_SUMSQ) || WM * WN != 8) return 1;
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+constexpr int gemm_lds_waves() {
   constexpr int pad = sizeof(T) == 4 ? 16 : 0;
   constexpr int lds = 2 * BK * (BM + BN + 2 * pad) * (int)sizeof(T) + 64;
   constexpr int wgs = (160 * 1024) / lds;
   constexpr int w = wgs * WM * WN / 4;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
+template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI>
+constexpr int gemm_min_waves() {
+  if ((EPI != EPI_RESID_STORE && EPI != EPI_SUMSQ) || WM * WN != 8) return 1;
+  return gemm_lds_waves<T, BM, BN, BK, WM, WN>();
+}
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ, bool FULL>
 __global__ void __launch_bounds__(64 * WM * WN)
 __attribute__((amdgpu_waves_per_eu(gemm_min_waves<T, BM, BN, BK, WM, WN, EPI>())))
 gemm_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int64_t kchunk, int mtc, int ntc,
@@ -326,8 +370,8 @@ gemm_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int64_t kchunk, int
   const int64_t n0 = (int64_t)nt * BN;
   const int64_t kb = (int64_t)blockIdx.y * kchunk;
   const int64_t ke = mn64(n0 >= ea.ncut ? mn64(K, ea.klim) : K, kb + kchunk);
-  gemm_tile<T, BM, BN, BK, WM, WN, EPI, VREQ>(X, Y, M, N, kb, ke, mt, nt, (int)blockIdx.y, q,
-                                               ea);
+  gemm_tile<T, BM, BN, BK, WM, WN, EPI, VREQ, FULL>(X, Y, M, N, kb, ke, mt, nt, (int)blockIdx.y,
+                                                     q, ea);
 }
 
 // Grouped form: many independent products in one launch.  Workgroup b finds its task t by
@@ -356,6 +400,70 @@ gemm_grouped_kernel(const GemmTask* __restrict__ tasks, const int* __restrict__ 
                                                tk.ea);
 }
 
+// Panel with a stream-K tail.  G resident workgroups first take the panel's tiles in rounds
+// of G, as the plain kernel does (tile r G + g in round r, so the tiles in flight at once are
+// consecutive and the row tiles of one column share its H panel in L2).  The tiles left over
+// (fewer than G; a plain launch would run them as a last round that leaves most of the chip
+// idle) are cut by (tile, K stage) iteration into G equal contiguous ranges, one per
+// workgroup.  A tile that one workgroup covers whole gets the panel epilogue; the pieces of a
+// shared tile go to tile-local partial slots in ea.red (slot 2g for workgroup g's first piece,
+// 2g + 1 for its last; only those two can be partial) and panel_fixup_kernel adds them in
+// workgroup order (deterministic) and writes the panel.  One tile instance serves both cases
+// (the slot, or -1, is a run-time argument); the iteration state costs registers, so the
+// kernel asks for the occupancy its LDS allows, at most 4 waves per SIMD.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int VREQ>
+__global__ void __launch_bounds__(64 * WM * WN)
+__attribute__((amdgpu_waves_per_eu(gemm_lds_waves<T, BM, BN, BK, WM, WN>() < 4
+                                       ? gemm_lds_waves<T, BM, BN, BK, WM, WN>() : 4)))
+panel_sk_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int mtc, int nk, int dp_rounds,
+                int64_t tail_total, int64_t Q, int per_xcd, EpiArgs ea) {
+  const int bx = blockIdx.x;
+  const int G = 8 * per_xcd;
+  const int64_t g = (int64_t)(bx & 7) * per_xcd + (bx >> 3);
+  for (int r = 0; r < dp_rounds; ++r) {
+    const int64_t t = (int64_t)r * G + g;
+    gemm_tile<T, BM, BN, BK, WM, WN, EPI_PANEL_SK, VREQ>(X, Y, M, N, 0, K, (int)(t % mtc),
+                                                        (int)(t / mtc), -1, 0, ea);
+  }
+  const int64_t t0 = (int64_t)dp_rounds * G;
+  int64_t it = g * Q;
+  const int64_t end = mn64(tail_total, it + Q);
+  bool first = true;
+  while (it < end) {
+    const int64_t tt = it / nk;
+    const int64_t k0 = it - tt * nk;
+    const int64_t k1 = mn64(nk, k0 + (end - it));
+    const int64_t t = t0 + tt;
+    const int slot = (k0 == 0 && k1 == nk) ? -1 : (int)(2 * g + (first ? 0 : 1));
+    gemm_tile<T, BM, BN, BK, WM, WN, EPI_PANEL_SK, VREQ>(X, Y, M, N, k0 * BK, mn64(K, k1 * BK),
+                                                        (int)(t % mtc), (int)(t / mtc), slot, 0,
+                                                        ea);
+    it += k1 - k0;
+    first = false;
+  }
+}
+
+// Tail tile t0 + blockIdx.x: sum its partial slots in workgroup order, write the panel.
+template <int BM, int BN>
+__global__ void __launch_bounds__(256)
+panel_fixup_kernel(const double* __restrict__ part, int64_t M, int64_t N, int mtc, int nk,
+                   int64_t t0, int64_t Q, EpiArgs ea) {
+  const int64_t tt = blockIdx.x, t = t0 + tt;
+  const int64_t g0 = tt * nk / Q, g1 = ((tt + 1) * nk - 1) / Q;
+  if (g0 == g1) return;  // written whole by one workgroup
+  const int64_t m0 = (t % mtc) * BM, n0 = (t / mtc) * BN;
+  for (int e = threadIdx.x; e < BM * BN; e += 256) {
+    const int64_t m = m0 + e / BN, n = n0 + e % BN;
+    if (m >= M || n >= N) continue;
+    double v = 0.0;
+    for (int64_t g = g0; g <= g1; ++g)
+      v += part[(2 * g + (g * Q >= tt * nk ? 0 : 1)) * (BM * BN) + e];
+    const int64_t gn = ea.g(n);
+    ea.out[(ea.s + m) * ea.ldo + gn] = -v;
+    ea.out[gn * ea.ldo + ea.s + m] = -v;
+  }
+}
+
 // The fast path also needs every per-thread offset (row-in-stage * ld + column + skip * ld)
 // to fit in 32 bits.
 template <typename T>
@@ -382,14 +490,22 @@ inline hipError_t launch_gemm(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N,
   const int gm = (EPI == EPI_RESID || EPI == EPI_RESID_STORE || EPI == EPI_SUMSQ) ? 8 : mtc;
   const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : (K > 0 ? K : 1);
   const dim3 grid(8 * per_xcd, splits > 1 ? splits : 1);
+  const int bk = d.bk;
+  // Every tile whole and every K range a whole number of stages: the branch-free loop.
+  const bool full = vec && M % d.bm == 0 && N % d.bn == 0 && K > 0 && K % bk == 0 &&
+                    kchunk % bk == 0 && (ea.ncut == INT64_MAX || ea.klim % bk == 0);
 #define IBMI_LAUNCH(BM_, BN_, BK_, WM_, WN_)                                                   \
   do {                                                                                         \
-    if (vec)                                                                                   \
-      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, VMAX>), grid,           \
+    if (full)                                                                                  \
+      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, VMAX, true>), grid,     \
+                         dim3(64 * WM_ * WN_), 0, st, X, Y, M, N, K, kchunk, mtc, ntc, per_xcd, \
+                         gm, ea);                                                              \
+    else if (vec)                                                                              \
+      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, VMAX, false>), grid,    \
                          dim3(64 * WM_ * WN_), 0, st, X, Y, M, N, K, kchunk, mtc, ntc, per_xcd, \
                          gm, ea);                                                              \
     else                                                                                       \
-      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, 1>), grid,              \
+      hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, BK_, WM_, WN_, EPI, 1, false>), grid,       \
                          dim3(64 * WM_ * WN_), 0, st, X, Y, M, N, K, kchunk, mtc, ntc, per_xcd, \
                          gm, ea);                                                              \
   } while (0)

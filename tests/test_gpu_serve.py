@@ -31,7 +31,8 @@ def test_serve_mix_equals_alone(srv):
         p = int(rng.integers(200, 1400))
         tol = 1e-6 if rid % 2 else 1e-10
         reqs.append(workloads.Request(rid, 0.0005 * rid, p, tol, int(rng.integers(0, 2**31 - 1))))
-    budgets = [serve.footprint_bytes(r.p, "fp64" if r.tol < 1e-6 else "fp32", 256, 32, r.tol)
+    budgets = [serve.footprint_bytes(r.p, "fp64" if r.tol < 1e-6 else serve.LOW_FORM, 256, 32,
+                                     r.tol)
                for r in reqs]
     budget = int(2.2 * max(budgets))
     loop = serve.ServeLoop(slots=3, hbm_budget=budget, block_rows=256, overlap=32, keep_h=True)
