@@ -26,7 +26,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PANEL_KERNEL = "gemm_kernel<double, 64, 64, 16, 2, 2, 1, 2>"
+PANEL_KERNEL = "gemm_kernel<double, 96, 64, 16, 2, 2, 1, 2, true>"
 # Update product of each low-precision form: (dense matrix-core peak of the instruction type
 # used, matrix-core products executed per FP32-level product, instruction type, kernel).
 UPDATE_KERNELS = {

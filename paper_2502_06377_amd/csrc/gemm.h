@@ -68,9 +68,8 @@ template <> struct Mfma<float> {
 // tiles go in groups of `gm` M-tiles per N column so the workgroups resident on one XCD share
 // operand panels in that XCD's L2.
 // ---------------------------------------------------------------------------------------
-// LDS of one tile configuration.  Declared in a function that does not depend on the
-// epilogue, so a kernel that runs the same tile code with two epilogues (stream-K panel) holds
-// one copy.  FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction;
+// LDS of one tile configuration, declared in a function that does not depend on the
+// epilogue (a kernel running the tile code with two epilogues would hold one copy).  FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction;
 // padding each row by 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left
 // unpadded (no bank conflicts measured).
 template <typename T, int BM, int BN, int BK, int NW>
@@ -279,14 +278,6 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
           ss += d * d;
         } else if constexpr (EPI == EPI_SUMSQ) {
           ss += v * v;
-        } else if constexpr (EPI == EPI_PANEL_SK) {
-          if (z >= 0) {  // a piece of a shared tile: tile-local partial slot z
-            ea.red[(int64_t)z * (BM * BN) + (m - m0) * BN + (n - n0)] = v;
-          } else {
-            const int64_t gn = ea.g(n);
-            ea.out[(ea.s + m) * ea.ldo + gn] = -v;
-            ea.out[gn * ea.ldo + ea.s + m] = -v;
-          }
         } else if constexpr (EPI == EPI_SUBFROM) {
           ea.out[m * ea.ldo + n] = ea.src[(ea.s + m) * ea.lds + n] - v;
         } else {
@@ -337,7 +328,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
 constexpr int gemm_lds_waves() {
   constexpr int pad = sizeof(T) == 4 ? 16 : 0;
-  constexpr int lds = 2 * BK * (BM + BN + 2 * pad) * (int)sizeof(T) + 64;
+  constexpr int lds = 2 * BK * (BM + BN + 2 * pad) * (int)sizeof(T);
   constexpr int wgs = (160 * 1024) / lds;
   constexpr int w = wgs * WM * WN / 4;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -398,70 +389,6 @@ gemm_grouped_kernel(const GemmTask* __restrict__ tasks, const int* __restrict__ 
   const int64_t ke = mn64(tk.K, kb + tk.kchunk);
   gemm_tile<T, BM, BN, BK, WM, WN, EPI, VREQ>(tk.X, tk.Y, tk.M, tk.N, kb, ke, mt, nt, z, local,
                                                tk.ea);
-}
-
-// Panel with a stream-K tail.  G resident workgroups first take the panel's tiles in rounds
-// of G, as the plain kernel does (tile r G + g in round r, so the tiles in flight at once are
-// consecutive and the row tiles of one column share its H panel in L2).  The tiles left over
-// (fewer than G; a plain launch would run them as a last round that leaves most of the chip
-// idle) are cut by (tile, K stage) iteration into G equal contiguous ranges, one per
-// workgroup.  A tile that one workgroup covers whole gets the panel epilogue; the pieces of a
-// shared tile go to tile-local partial slots in ea.red (slot 2g for workgroup g's first piece,
-// 2g + 1 for its last; only those two can be partial) and panel_fixup_kernel adds them in
-// workgroup order (deterministic) and writes the panel.  One tile instance serves both cases
-// (the slot, or -1, is a run-time argument); the iteration state costs registers, so the
-// kernel asks for the occupancy its LDS allows, at most 4 waves per SIMD.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int VREQ>
-__global__ void __launch_bounds__(64 * WM * WN)
-__attribute__((amdgpu_waves_per_eu(gemm_lds_waves<T, BM, BN, BK, WM, WN>() < 4
-                                       ? gemm_lds_waves<T, BM, BN, BK, WM, WN>() : 4)))
-panel_sk_kernel(Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K, int mtc, int nk, int dp_rounds,
-                int64_t tail_total, int64_t Q, int per_xcd, EpiArgs ea) {
-  const int bx = blockIdx.x;
-  const int G = 8 * per_xcd;
-  const int64_t g = (int64_t)(bx & 7) * per_xcd + (bx >> 3);
-  for (int r = 0; r < dp_rounds; ++r) {
-    const int64_t t = (int64_t)r * G + g;
-    gemm_tile<T, BM, BN, BK, WM, WN, EPI_PANEL_SK, VREQ>(X, Y, M, N, 0, K, (int)(t % mtc),
-                                                        (int)(t / mtc), -1, 0, ea);
-  }
-  const int64_t t0 = (int64_t)dp_rounds * G;
-  int64_t it = g * Q;
-  const int64_t end = mn64(tail_total, it + Q);
-  bool first = true;
-  while (it < end) {
-    const int64_t tt = it / nk;
-    const int64_t k0 = it - tt * nk;
-    const int64_t k1 = mn64(nk, k0 + (end - it));
-    const int64_t t = t0 + tt;
-    const int slot = (k0 == 0 && k1 == nk) ? -1 : (int)(2 * g + (first ? 0 : 1));
-    gemm_tile<T, BM, BN, BK, WM, WN, EPI_PANEL_SK, VREQ>(X, Y, M, N, k0 * BK, mn64(K, k1 * BK),
-                                                        (int)(t % mtc), (int)(t / mtc), slot, 0,
-                                                        ea);
-    it += k1 - k0;
-    first = false;
-  }
-}
-
-// Tail tile t0 + blockIdx.x: sum its partial slots in workgroup order, write the panel.
-template <int BM, int BN>
-__global__ void __launch_bounds__(256)
-panel_fixup_kernel(const double* __restrict__ part, int64_t M, int64_t N, int mtc, int nk,
-                   int64_t t0, int64_t Q, EpiArgs ea) {
-  const int64_t tt = blockIdx.x, t = t0 + tt;
-  const int64_t g0 = tt * nk / Q, g1 = ((tt + 1) * nk - 1) / Q;
-  if (g0 == g1) return;  // written whole by one workgroup
-  const int64_t m0 = (t % mtc) * BM, n0 = (t / mtc) * BN;
-  for (int e = threadIdx.x; e < BM * BN; e += 256) {
-    const int64_t m = m0 + e / BN, n = n0 + e % BN;
-    if (m >= M || n >= N) continue;
-    double v = 0.0;
-    for (int64_t g = g0; g <= g1; ++g)
-      v += part[(2 * g + (g * Q >= tt * nk ? 0 : 1)) * (BM * BN) + e];
-    const int64_t gn = ea.g(n);
-    ea.out[(ea.s + m) * ea.ldo + gn] = -v;
-    ea.out[gn * ea.ldo + ea.s + m] = -v;
-  }
 }
 
 // The fast path also needs every per-thread offset (row-in-stage * ld + column + skip * ld)

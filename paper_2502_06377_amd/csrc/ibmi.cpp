@@ -121,8 +121,9 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
   return (i >= 0 && i < ibmi::GEMM_CFG_COUNT) ? (GemmCfg)i : dflt;
 }
 
-// Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel and
-// diagonal products favour small tiles with many resident waves, the square residual the
+// Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel 96x64
+// tiles (six row tiles cover a 576-row set; 0.76 of the FP64 peak against 0.71 for 64x64),
+// the diagonal product 64x64 tiles with many resident waves, the square residual the
 // 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 96x128 tiles
 // (two terms) or 6-wave 192x128 tiles (three terms) with K cut into chunks of 2048 (the few
 // row tiles of a 576-row set times eight chunks fill the chip where whole-K tiles leave it
@@ -135,7 +136,6 @@ struct Tuning {
   SplitCfg split = ibmi::SPLIT_96x128;   // split-bfloat16 update product, two terms
   SplitCfg split6 = ibmi::SPLIT_192x128; // the same with three terms
   int64_t split_kchunk = 2048;           // their K chunk (0: whole K per tile)
-  bool panel_sk = true;                  // stream-K panel for panels of many tiles
 };
 
 Tuning tuning_for(int64_t p) {
@@ -143,6 +143,7 @@ Tuning tuning_for(int64_t p) {
   if (p < 2048) {  // small matrices: more, smaller tiles
     t.resid = ibmi::GEMM_64x64_K16;
   }
+  if (p >= 8192) t.panel = ibmi::GEMM_96x64_K16;  // enough column tiles to fill the chip
   t.upd32 = env_cfg("IBMI_CFG_UPD32", t.upd32);
   t.panel = env_cfg("IBMI_CFG_PANEL", t.panel);
   t.diag = env_cfg("IBMI_CFG_DIAG", t.diag);
@@ -154,7 +155,6 @@ Tuning tuning_for(int64_t p) {
     if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = t.split6 = (SplitCfg)i;
   }
   if (const char* v = std::getenv("IBMI_SPLIT_KCHUNK")) t.split_kchunk = std::max(0, std::atoi(v));
-  if (const char* v = std::getenv("IBMI_PANEL_SK")) t.panel_sk = std::atoi(v) != 0;
   return t;
 }
 
@@ -182,7 +182,6 @@ int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
   size_t desc = 0, fac = 0, wt = 0, part = 0, red = 0, red2 = 0, scal = 0, status = 0, total = 0;
-  size_t psk = 0, psk_bytes = 0;  // stream-K panel partials (none when unused)
   // Correction (FP32 / split-bfloat16 update) forms only (zero size otherwise)
   size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, x2 = 0, spart = 0;
   int64_t ld32 = 0;  // row stride of the FP32 copies of A and D (multiple of 4)
@@ -232,15 +231,6 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
   off = align_up(off + 8 * 8);
   L.status = off;
   off = align_up(off + 4 * sizeof(int));
-  // Stream-K panel partials, for plans whose panels are several times the resident workgroups.
-  int64_t panel_tiles = 0;
-  for (int k = 0; k < K; ++k)
-    panel_tiles = std::max(panel_tiles, ibmi::gemm_tiles(t.panel, e[k] - s[k], p - (e[k] - s[k])));
-  if (t.panel_sk && panel_tiles > 512) {
-    L.psk = off;
-    L.psk_bytes = ibmi::panel_sk_part_bytes(t.panel);
-    off = align_up(off + L.psk_bytes);
-  }
   if (o->precision != IBMI_PREC_FP64) {
     L.ld32 = (p + 3) / 4 * 4;
     const size_t pp = (size_t)p * L.ld32;
@@ -526,8 +516,7 @@ static ibmi_status block_step(ibmi_plan_t P, double* dH, int64_t ldh, int k) {
   Opnd Xw{P->wt(k), b, IdxMap{}, IdxMap{}};
   Opnd Yp{dH, ldh, g, g};
   hipEvent_t ev = prof_begin(P, 0);
-  IBMI_HIP(ibmi::gemm_panel_sk(P->t.panel, Xw, Yp, b, c, c, dH, ldh, s, g,
-                               P->L.psk_bytes ? (double*)(P->work + P->L.psk) : nullptr, st));
+  IBMI_HIP(ibmi::gemm_panel(P->t.panel, Xw, Yp, b, c, c, dH, ldh, s, g, st));
   prof_end(P, 0, ev, 2.0 * b * (double)c * c);
   const int splits = diag_splits_for(b, c, P->t.diag, P->t.diag_splits);
   Opnd Yd{dH, ldh, g, IdxMap{s, INT64_MAX, 0}};

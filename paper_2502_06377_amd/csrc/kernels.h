@@ -42,8 +42,7 @@ enum {
   EPI_RESID_STORE = 4,  // out[m][n] = delta_mn - C and red[slot] = sum of its squares
   EPI_SUBFROM = 5,      // out[m][n] = src[(s+m)][n] - C
   EPI_CORR = 6,         // correction of H[I^c,I] and D (FP32-update form)
-  EPI_SUMSQ = 7,        // red[slot] = sum over the tile of C^2
-  EPI_PANEL_SK = 8      // EPI_PANEL (z < 0) or red[z][m - m0][n - n0] = C (stream-K piece)
+  EPI_SUMSQ = 7         // red[slot] = sum over the tile of C^2
 };
 
 struct EpiArgs {
@@ -124,13 +123,6 @@ hipError_t gemm_store(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t
                       double* out, int64_t ldo, hipStream_t st);
 hipError_t gemm_panel(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
                       double* H, int64_t ldh, int64_t s, IdxMap g, hipStream_t st);
-// The same product as a stream-K launch when part (panel_sk_part_bytes(cfg) bytes) is given
-// and the panel has more tiles than resident workgroups; a plain launch otherwise.
-constexpr int kSkMaxWorkgroups = 2048;
-size_t panel_sk_part_bytes(GemmCfg cfg);
-hipError_t gemm_panel_sk(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
-                         double* H, int64_t ldh, int64_t s, IdxMap g, double* part,
-                         hipStream_t st);
 hipError_t gemm_partial(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, int64_t K,
                         int splits, double* out, hipStream_t st);
 // Writes one partial sum of (delta_mn - C)^2 per tile to red (gemm_tiles of them) and their
