@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-forms", default="fp32,bf16x3,bf16x6",
                     help="low-precision update forms timed beside the FP64 form")
-    ap.add_argument("--cpu-sets", type=int, default=12)
+    ap.add_argument("--cpu-sets", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()

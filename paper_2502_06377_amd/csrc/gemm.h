@@ -93,11 +93,11 @@ struct VecWidth {
 
 // Work of one output tile: rows [mt*BM, ..) and columns [nt*BN, ..) of C, summed over k in
 // [kb, ke), which is K chunk `z` of a split-K product; `slot` is where the residual
-// epilogues put this tile's partial sum.  FULL: the caller guarantees that the tile lies
-// inside M x N and that ke - kb is a multiple of BK (with VEC-wide loads valid), so the
-// K loop has no branches: that keeps the accumulators in the matrix-core registers across
-// iterations (with a branch in the loop the compiler copies all of them out and back every
-// stage).
+// epilogues put this tile's partial sum.  FULL: the caller guarantees VEC-wide loads are
+// valid, M and N are multiples of VEC and ke - kb is a multiple of BK, so every stage takes
+// the vector load path and the K loop has no branches.  Edge tiles then load the last valid
+// VEC columns in place of the columns past M (N): those only feed outputs past M (N), which
+// are never stored.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI, int VREQ, bool FULL = false>
 __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t M, int64_t N,
                                           int64_t kb, int64_t ke, int mt, int nt, int z,
@@ -145,13 +145,15 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   for (int v = 0; v < XV; ++v) {
     const int idx = (tid + v * NT) * VEC;
     xkk[v] = idx / BM;
-    xoff[v] = interior ? xkk[v] * (int)X.ld + (int)X.c(m0 + idx % BM) : 0;
+    const int64_t m = FULL ? mn64(m0 + idx % BM, M - VEC) : m0 + idx % BM;
+    xoff[v] = interior ? xkk[v] * (int)X.ld + (int)X.c(m) : 0;
   }
 #pragma unroll
   for (int v = 0; v < YV; ++v) {
     const int idx = (tid + v * NT) * VEC;
     ykk[v] = idx / BN;
-    yoff[v] = interior ? ykk[v] * (int)Y.ld + (int)Y.c(n0 + idx % BN) : 0;
+    const int64_t n = FULL ? mn64(n0 + idx % BN, N - VEC) : n0 + idx % BN;
+    yoff[v] = interior ? ykk[v] * (int)Y.ld + (int)Y.c(n) : 0;
   }
   const int xskipld = (int)(X.r.skip * X.ld), yskipld = (int)(Y.r.skip * Y.ld);
 
@@ -415,12 +417,14 @@ inline hipError_t launch_gemm(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N,
   // Square residual-type products walk groups of 8 row tiles; the panel and diagonal
   // products (few row tiles) walk whole columns.
   const int gm = (EPI == EPI_RESID || EPI == EPI_RESID_STORE || EPI == EPI_SUMSQ) ? 8 : mtc;
-  const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : (K > 0 ? K : 1);
-  const dim3 grid(8 * per_xcd, splits > 1 ? splits : 1);
   const int bk = d.bk;
-  // Every tile whole and every K range a whole number of stages: the branch-free loop.
-  const bool full = vec && M % d.bm == 0 && N % d.bn == 0 && K > 0 && K % bk == 0 &&
-                    kchunk % bk == 0 && (ea.ncut == INT64_MAX || ea.klim % bk == 0);
+  // Split-K chunks are whole stages, so that with K a multiple of BK every K range is.
+  const int64_t kchunk =
+      splits > 1 ? ((K + splits - 1) / splits + bk - 1) / bk * bk : (K > 0 ? K : 1);
+  const dim3 grid(8 * per_xcd, splits > 1 ? splits : 1);
+  // Every K range a whole number of stages and M, N whole vectors: the branch-free loop.
+  const bool full = vec && M % VMAX == 0 && N % VMAX == 0 && K > 0 && K % bk == 0 &&
+                    (ea.ncut == INT64_MAX || ea.klim % bk == 0 || ea.klim >= K);
 #define IBMI_LAUNCH(BM_, BN_, BK_, WM_, WN_)                                                   \
   do {                                                                                         \
     if (full)                                                                                  \

@@ -13,7 +13,10 @@ hipError_t gemm_f32_subfrom(GemmCfg cfg, Opnd X, Opnd Y, int64_t M, int64_t N, i
   ea.lds = lds;
   ea.s = s;
   ea.ncut = ncut;
-  ea.klim = klim;
+  // Rows klim .. of Y are zero in the column tiles that stop at klim, so rounding klim up
+  // to whole K stages adds only zeros and keeps the loop branch-free.
+  const int64_t bk = gemm_dims(cfg).bk;
+  ea.klim = std::min(K, (klim + bk - 1) / bk * bk);
   return launch_gemm<float, EPI_SUBFROM>(cfg, X, Y, M, N, K, 1, ea, st, nullptr);
 }
 

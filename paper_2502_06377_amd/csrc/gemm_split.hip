@@ -314,6 +314,9 @@ hipError_t gemm_split_subfrom(SplitCfg cfg, int terms, const float* X, int64_t l
   a.M = M;
   a.N = N;
   a.K = K;
+  // Rows klim .. of Y are zero in the column tiles that stop at klim: rounding up to whole
+  // stages adds zeros only and spares those tiles a ragged last stage.
+  klim = std::min(K, (std::max<int64_t>(klim, 0) + d.bk - 1) / d.bk * d.bk);
   a.klim = klim;
   a.kchunk = kchunk;
   a.mtc = (int)((M + d.bm - 1) / d.bm);
