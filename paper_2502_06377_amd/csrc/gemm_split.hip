@@ -77,7 +77,10 @@ struct SplitArgs {
 // Workgroup tile BM x BN over WM x WN waves (each wave (BM/WM) x (BN/WN) of 16x16 tiles);
 // K staged BK at a time through double-buffered LDS.  Rows of the LDS tiles are padded by
 // 16 bytes so the 16 rows one matrix instruction reads fall on distinct banks.
-template <int BM, int BN, int BK, int WM, int WN, int TERMS>
+// FULL: every K range is a whole number of stages, so every stage takes the vector loads and
+// the loop has no branches; rows past M (N) load the last valid row instead, which only feeds
+// outputs that are never stored.
+template <int BM, int BN, int BK, int WM, int WN, int TERMS, bool FULL>
 __global__ void __launch_bounds__(64 * WM * WN) split_gemm_kernel(SplitArgs a) {
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -128,24 +131,36 @@ __global__ void __launch_bounds__(64 * WM * WN) split_gemm_kernel(SplitArgs a) {
   const int lr = lane & 15, lk = lane >> 4;
 
   // Loads: float4 f = tid + v * NT of a stage covers row f / KQ, k offset 4 * (f % KQ).
-  const bool rows_in = m0 + BM <= a.M && n0 + BN <= a.N;
-  const float* xbase = a.X + (a.xrow0 + m0) * a.ldx;
-  const float* ybase = a.Y + n0 * a.ldy;
+  const bool rows_in = FULL || (m0 + BM <= a.M && n0 + BN <= a.N);
+  const float* xbase = a.X + a.xrow0 * a.ldx;
+  int64_t xo[XL], yo[YL];  // per-thread row offsets (rows clamped in the full form)
+#pragma unroll
+  for (int v = 0; v < XL; ++v) {
+    const int f = tid + v * NT;
+    const int64_t m = FULL ? smin64(m0 + f / KQ, a.M - 1) : m0 + f / KQ;
+    xo[v] = m * a.ldx + 4 * (f % KQ);
+  }
+#pragma unroll
+  for (int v = 0; v < YL; ++v) {
+    const int f = tid + v * NT;
+    const int64_t n = FULL ? smin64(n0 + f / KQ, a.N - 1) : n0 + f / KQ;
+    yo[v] = n * a.ldy + 4 * (f % KQ);
+  }
   float4 xr[XL], yr[YL];
   auto gload = [&](int kt_) {
     const int64_t k0 = kb + (int64_t)kt_ * BK;
-    if (rows_in && k0 + BK <= ke) {
+    if (FULL || (rows_in && k0 + BK <= ke)) {
 #pragma unroll
       for (int v = 0; v < XL; ++v) {
         const int f = tid + v * NT;
         if (!XFULL && f >= BM * KQ) continue;
-        xr[v] = *(const float4*)(xbase + (int64_t)(f / KQ) * a.ldx + k0 + 4 * (f % KQ));
+        xr[v] = *(const float4*)(xbase + xo[v] + k0);
       }
 #pragma unroll
       for (int v = 0; v < YL; ++v) {
         const int f = tid + v * NT;
         if (!YFULL && f >= BN * KQ) continue;
-        yr[v] = *(const float4*)(ybase + (int64_t)(f / KQ) * a.ldy + k0 + 4 * (f % KQ));
+        yr[v] = *(const float4*)(a.Y + yo[v] + k0);
       }
       return;
     }
@@ -199,14 +214,7 @@ __global__ void __launch_bounds__(64 * WM * WN) split_gemm_kernel(SplitArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v4f_t{0, 0, 0, 0};
 
-  if (nk > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    if (it + 1 < nk) gload(it + 1);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       bf16x8 xa[TERMS][TM], yb[TERMS][TN];
@@ -231,9 +239,22 @@ __global__ void __launch_bounds__(64 * WM * WN) split_gemm_kernel(SplitArgs a) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[ti][i], yb[d - ti][j],
                                                                   acc[i][j], 0, 0, 0);
     }
-    if (it + 1 < nk) sstore(cur ^ 1);
+  };
+
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  // The next stage's loads are in flight while the matrix cores work on the current one; the
+  // last stage is peeled so the loop body has no conditions.
+  for (int it = 0; it + 1 < nk; ++it) {
+    gload(it + 1);
+    compute(it & 1);
+    sstore((it + 1) & 1);
     __syncthreads();
   }
+  if (nk > 0) compute((nk - 1) & 1);
 
   // Result layout of the 16x16 FP32-accumulating instructions: register r of lane l holds
   // row 4 (l / 16) + r, column l % 16.
@@ -337,13 +358,21 @@ hipError_t gemm_split_subfrom(SplitCfg cfg, int terms, const float* X, int64_t l
   a.part = part;
   if (!a.direct && !part) return hipErrorInvalidValue;
   const dim3 grid(8 * a.per_xcd);
+  // Whole stages everywhere (K, the chunks and the rounded klim are multiples of BK).
+  const bool full = K % d.bk == 0;
 #define IBMI_SCASE(NAME, BM_, BN_, BK_, WM_, WN_)                                              \
   case NAME:                                                                                   \
-    if (terms == 2)                                                                            \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 2>), grid,                \
+    if (terms == 2 && full)                                                                    \
+      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 2, true>), grid,          \
+                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
+    else if (terms == 2)                                                                       \
+      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 2, false>), grid,         \
+                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
+    else if (full)                                                                             \
+      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 3, true>), grid,          \
                          dim3(64 * WM_ * WN_), 0, st, a);                                      \
     else                                                                                       \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 3>), grid,                \
+      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 3, false>), grid,         \
                          dim3(64 * WM_ * WN_), 0, st, a);                                      \
     break;
   switch (cfg) {
