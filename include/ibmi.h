@@ -231,7 +231,7 @@ ibmi_status ibmi_batch_plan(ibmi_batch_t* out, int32_t n, const int64_t* p,
 ibmi_status ibmi_batch_solve(ibmi_batch_t batch, double* const* dH, const int64_t* ldh,
                              ibmi_info* infos);
 
-/* Tile configurations (0 <= cfg < 12; see the GEMM configuration table in the sources) of
+/* Tile configurations (0 <= cfg < 11; see the GEMM configuration table in the sources) of
  * the grouped panel, diagonal and residual launches. */
 ibmi_status ibmi_batch_set_tuning(ibmi_batch_t batch, int32_t panel, int32_t diag,
                                   int32_t resid);

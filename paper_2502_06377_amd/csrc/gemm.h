@@ -320,8 +320,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   X_(GEMM_32x64_W1, 32, 64, 16, 1, 1)                                                          \
   X_(GEMM_64x64_W2, 64, 64, 32, 2, 1)                                                          \
   X_(GEMM_96x128, 96, 128, 32, 2, 2)                                                           \
-  X_(GEMM_192x96, 192, 96, 16, 2, 2)                                                           \
-  X_(GEMM_256x128_W8, 256, 128, 16, 4, 2)
+  X_(GEMM_192x96, 192, 96, 16, 2, 2)
 
 // Waves per SIMD that the LDS of one workgroup allows (160 KiB per CU, 4 SIMDs), capped at 8.
 // The 8-wave tiles of the residual epilogues that store or square the product ask the

@@ -105,8 +105,7 @@ enum GemmCfg {
   GEMM_64x64_W2 = 8,    // 2x1 waves of 32x64 ( 8 chains), BK 32
   GEMM_96x128 = 9,      // 2x2 waves of 48x64 (12 chains), BK 32
   GEMM_192x96 = 10,     // 2x2 waves of 96x48 (18 chains), BK 16
-  GEMM_256x128_W8 = 11, // 4x2 waves of 64x64 (16 chains), BK 16
-  GEMM_CFG_COUNT = 12
+  GEMM_CFG_COUNT = 11
 };
 struct GemmDims {
   int bm, bn, bk;
