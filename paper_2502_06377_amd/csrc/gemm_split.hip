@@ -36,26 +36,21 @@ typedef uint2 __attribute__((may_alias)) uint2_a;
 
 __device__ __forceinline__ int64_t smin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
-// Bits of bf16(v) (round to nearest even) in the upper half of a word; finite v.
-__device__ __forceinline__ uint32_t bf16_rne(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-}
-
-// The TERMS bfloat16 terms of four consecutive values, each term packed as 4 x 16 bits.
+// The TERMS bfloat16 terms of four consecutive values, each term packed as 4 x 16 bits.  The
+// conversion rounds to nearest even (one v_cvt_pk_bf16_f32 per pair of values on gfx950);
+// converting back to FP32 and subtracting is exact.
 template <int TERMS>
 __device__ __forceinline__ void split4(const float4 v, uint2 (&out)[TERMS]) {
   float r[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int t = 0; t < TERMS; ++t) {
-    uint32_t b[4];
+    __bf16 b[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      b[e] = bf16_rne(r[e]);
-      r[e] = r[e] - __uint_as_float(b[e]);
+      b[e] = (__bf16)r[e];
+      r[e] = r[e] - (float)b[e];
     }
-    out[t].x = (b[0] >> 16) | (b[1] & 0xFFFF0000u);
-    out[t].y = (b[2] >> 16) | (b[3] & 0xFFFF0000u);
+    __builtin_memcpy(&out[t], b, sizeof(b));
   }
 }
 
