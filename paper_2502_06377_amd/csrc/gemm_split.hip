@@ -36,21 +36,27 @@ typedef uint2 __attribute__((may_alias)) uint2_a;
 
 __device__ __forceinline__ int64_t smin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
-// The TERMS bfloat16 terms of four consecutive values, each term packed as 4 x 16 bits.  The
-// conversion rounds to nearest even (one v_cvt_pk_bf16_f32 per pair of values on gfx950);
-// converting back to FP32 and subtracting is exact.
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
+
+// The TERMS bfloat16 terms of four consecutive values, each term packed as 4 x 16 bits.  Each
+// pair converts with one v_cvt_pk_bf16_f32 (round to nearest even); converting back to FP32
+// (a shift) and subtracting is exact.
 template <int TERMS>
 __device__ __forceinline__ void split4(const float4 v, uint2 (&out)[TERMS]) {
-  float r[4] = {v.x, v.y, v.z, v.w};
+  v2f_t r0 = {v.x, v.y}, r1 = {v.z, v.w};
 #pragma unroll
   for (int t = 0; t < TERMS; ++t) {
-    __bf16 b[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      b[e] = (__bf16)r[e];
-      r[e] = r[e] - (float)b[e];
+    const v2bf_t b0 = __builtin_convertvector(r0, v2bf_t);
+    const v2bf_t b1 = __builtin_convertvector(r1, v2bf_t);
+    uint32_t u0, u1;
+    __builtin_memcpy(&u0, &b0, 4);
+    __builtin_memcpy(&u1, &b1, 4);
+    out[t] = make_uint2(u0, u1);
+    if (t + 1 < TERMS) {
+      r0 -= v2f_t{__uint_as_float(u0 << 16), __uint_as_float(u0 & 0xFFFF0000u)};
+      r1 -= v2f_t{__uint_as_float(u1 << 16), __uint_as_float(u1 & 0xFFFF0000u)};
     }
-    __builtin_memcpy(&out[t], b, sizeof(b));
   }
 }
 
@@ -291,7 +297,25 @@ __global__ void split_finalize_kernel(const float* __restrict__ part, int64_t M,
   X_(SPLIT_96x128, 96, 128, 32, 2, 2)   \
   X_(SPLIT_192x128, 192, 128, 32, 3, 2) \
   X_(SPLIT_144x128, 144, 128, 32, 3, 2) \
-  X_(SPLIT_64x64, 64, 64, 32, 1, 1)
+  X_(SPLIT_64x64, 64, 64, 32, 1, 1)     \
+  X_(SPLIT_192x256, 192, 256, 32, 2, 4)
+
+// One configuration and term count; configurations whose LDS would not fit (160 KiB per
+// workgroup) with three terms are rejected.
+template <int BM, int BN, int BK, int WM, int WN, int TERMS>
+hipError_t launch_split(bool full, dim3 grid, const SplitArgs& a, hipStream_t st) {
+  if constexpr (2 * TERMS * (BM + BN) * (BK + 8) * 2 > 160 * 1024) {
+    return hipErrorInvalidValue;
+  } else {
+    if (full)
+      hipLaunchKernelGGL((split_gemm_kernel<BM, BN, BK, WM, WN, TERMS, true>), grid,
+                         dim3(64 * WM * WN), 0, st, a);
+    else
+      hipLaunchKernelGGL((split_gemm_kernel<BM, BN, BK, WM, WN, TERMS, false>), grid,
+                         dim3(64 * WM * WN), 0, st, a);
+    return hipGetLastError();
+  }
+}
 
 }  // namespace
 
@@ -355,27 +379,17 @@ hipError_t gemm_split_subfrom(SplitCfg cfg, int terms, const float* X, int64_t l
   const dim3 grid(8 * a.per_xcd);
   // Whole stages everywhere (K, the chunks and the rounded klim are multiples of BK).
   const bool full = K % d.bk == 0;
-#define IBMI_SCASE(NAME, BM_, BN_, BK_, WM_, WN_)                                              \
-  case NAME:                                                                                   \
-    if (terms == 2 && full)                                                                    \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 2, true>), grid,          \
-                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
-    else if (terms == 2)                                                                       \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 2, false>), grid,         \
-                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
-    else if (full)                                                                             \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 3, true>), grid,          \
-                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
-    else                                                                                       \
-      hipLaunchKernelGGL((split_gemm_kernel<BM_, BN_, BK_, WM_, WN_, 3, false>), grid,         \
-                         dim3(64 * WM_ * WN_), 0, st, a);                                      \
+#define IBMI_SCASE(NAME, BM_, BN_, BK_, WM_, WN_)                                       \
+  case NAME:                                                                            \
+    e = terms == 2 ? launch_split<BM_, BN_, BK_, WM_, WN_, 2>(full, grid, a, st)        \
+                   : launch_split<BM_, BN_, BK_, WM_, WN_, 3>(full, grid, a, st);       \
     break;
+  hipError_t e = hipSuccess;
   switch (cfg) {
     IBMI_SPLIT_CONFIGS(IBMI_SCASE)
     default: return hipErrorInvalidValue;
   }
 #undef IBMI_SCASE
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.direct) return e;
   const int64_t total = M * N;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);

@@ -152,7 +152,11 @@ Tuning tuning_for(int64_t p) {
   if (const char* v = std::getenv("IBMI_DIAG_SPLITS")) t.diag_splits = std::max(1, std::atoi(v));
   if (const char* v = std::getenv("IBMI_CFG_SPLIT")) {
     const int i = std::atoi(v);
-    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = t.split6 = (SplitCfg)i;
+    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split = (SplitCfg)i;
+  }
+  if (const char* v = std::getenv("IBMI_CFG_SPLIT6")) {
+    const int i = std::atoi(v);
+    if (i >= 0 && i < ibmi::SPLIT_CFG_COUNT) t.split6 = (SplitCfg)i;
   }
   if (const char* v = std::getenv("IBMI_SPLIT_KCHUNK")) t.split_kchunk = std::max(0, std::atoi(v));
   return t;

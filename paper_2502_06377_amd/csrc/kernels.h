@@ -155,7 +155,8 @@ enum SplitCfg {
   SPLIT_192x128 = 3,  // 3x2 waves of 64x64
   SPLIT_144x128 = 4,  // 3x2 waves of 48x64
   SPLIT_64x64 = 5,    // 1 wave of 64x64
-  SPLIT_CFG_COUNT = 6
+  SPLIT_192x256 = 6,  // 2x4 waves of 96x64
+  SPLIT_CFG_COUNT = 7
 };
 struct SplitDims {
   int bm, bn, bk;
