@@ -30,9 +30,12 @@ PANEL_KERNEL = "gemm_kernel<double, 96, 64, 16, 2, 2, 1, 2, true>"
 # Update product of each low-precision form: (dense matrix-core peak of the instruction type
 # used, matrix-core products executed per FP32-level product, instruction type, kernel).
 UPDATE_KERNELS = {
-    "fp32": (157.3, 1, "f32", "gemm_kernel<float, 64, 64, 32, 2, 2, 5, 4> (R[I,:] - A[I,:] D)"),
-    "bf16x3": (2500.0, 3, "bf16", "split_gemm_kernel<96, 128, 32, 2, 2, 2> (R[I,:] - A[I,:] D)"),
-    "bf16x6": (2500.0, 6, "bf16", "split_gemm_kernel<192, 128, 32, 3, 2, 3> (R[I,:] - A[I,:] D)"),
+    "fp32": (157.3, 1, "f32",
+             "gemm_kernel<float, 64, 64, 32, 2, 2, 5, 4, true> (R[I,:] - A[I,:] D)"),
+    "bf16x3": (2500.0, 3, "bf16",
+               "split_gemm_kernel<192, 256, 32, 2, 4, 2, true> (R[I,:] - A[I,:] D)"),
+    "bf16x6": (2500.0, 6, "bf16",
+               "split_gemm_kernel<192, 128, 32, 3, 2, 3, true> (R[I,:] - A[I,:] D)"),
 }
 
 

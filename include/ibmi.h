@@ -80,7 +80,16 @@ typedef enum { IBMI_INIT_IDENTITY = 0, IBMI_INIT_BLOCKDIAG_INV = 1, IBMI_INIT_GI
  *            other sweeps is that prediction (inf before the first evaluation), and only an
  *            evaluated bound can stop the solve.  With fixed_sweeps the last sweep is
  *            evaluated.  Needs p * p * 8 more workspace bytes in the FP64 form. */
-typedef enum { IBMI_STOP_FRO = 0, IBMI_STOP_REL_BOUND = 1, IBMI_STOP_REL_HR = 2 } ibmi_stop;
+/* PAPER:     ||(H A)[I_K, I_K^c]||_F < tol for the last set I_K: the paper's eq. (error)
+ *            estimate (the (1,2) block of H A, which vanishes at A^{-1}) in the Frobenius norm,
+ *            an upper bound of the spectral norm the paper uses.  Costs a 2 b p (p - b)
+ *            product per sweep on top of the residual, which is still reported. */
+typedef enum {
+  IBMI_STOP_FRO = 0,
+  IBMI_STOP_REL_BOUND = 1,
+  IBMI_STOP_REL_HR = 2,
+  IBMI_STOP_PAPER = 3
+} ibmi_stop;
 
 typedef struct {
   int64_t p;               /* order of A                                                  */

@@ -164,14 +164,15 @@ def residual_fro(a: np.ndarray, h: np.ndarray) -> float:
     return float(np.sqrt(np.sum(r * r)))
 
 
-def paper_error(a: np.ndarray, h: np.ndarray, idx: np.ndarray) -> float:
-    """The paper's stopping estimate, eq. (error): ||H_I A_{I,I^c} + H_{I,I^c} A_{I^c}||_2,
-    the (1,2) block of H A for set I (spectral norm)."""
+def paper_error(a: np.ndarray, h: np.ndarray, idx: np.ndarray, norm: str = "2") -> float:
+    """The paper's stopping estimate, eq. (error): ||H_I A_{I,I^c} + H_{I,I^c} A_{I^c}||,
+    the (1,2) block of H A for set I, in the spectral norm (``norm="2"``, the paper's) or the
+    Frobenius norm (``"fro"``, an upper bound of it, the run-time stop test)."""
     ic = complement(a.shape[0], idx)
     if ic.size == 0:
         return 0.0
     e = h[np.ix_(idx, idx)] @ a[np.ix_(idx, ic)] + h[np.ix_(idx, ic)] @ a[np.ix_(ic, ic)]
-    return float(np.linalg.norm(e, 2))
+    return float(np.linalg.norm(e, 2 if norm == "2" else "fro"))
 
 
 def hr_error_bound(a: np.ndarray, h: np.ndarray) -> tuple:
@@ -227,7 +228,9 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
     costs a second p^3 product, so it is evaluated only at some sweeps: when ||R||_F < 1 for
     the first time, when ||R||_F has fallen tenfold since the last evaluation, and when the
     last evaluation's ratio bound/||R||_F times the current ||R||_F is below tol; at other
-    sweeps the stop value is that prediction (inf before the first evaluation).  The loop always runs at
+    sweeps the stop value is that prediction (inf before the first evaluation).
+    ``stop="paper"`` stops once the Frobenius form of the paper's eq. (error) estimate for the
+    last set, ||(H A)[I_K, I_K^c]||_F, is below tol.  The loop always runs at
     least one sweep, and returns H after ``max_sweeps`` with converged=False when the test
     never passes.  Stagnation guard (the FP64 floor of ||I - A H||_F can lie above tol):
     stop with floor_limited=True once the best stop value so far (the quantity compared with
@@ -261,7 +264,8 @@ def ibmi_solve(a, blocks, init: str = "identity", h0=None, tol: float = 1e-10,
             else:
                 sv = ratio * rho if ratio is not None else float("inf")
         else:
-            sv = _stop_value(a, h, rho, stop, lam_min)
+            sv = (paper_error(a, h, bp[-1].idx, "fro") if stop == "paper"
+                  else _stop_value(a, h, rho, stop, lam_min))
         res.stop_value = sv
         if sv < 0.99 * best:
             best, since_best = sv, 0

@@ -28,11 +28,12 @@ IBMI_OK, IBMI_ERR_INVALID_ARG, IBMI_ERR_NOT_SPD, IBMI_ERR_OUT_OF_MEMORY, IBMI_ER
     IBMI_ERR_NONFINITE = range(6)
 IBMI_PREC_FP64, IBMI_PREC_FP32_UPDATE, IBMI_PREC_BF16X3_UPDATE, IBMI_PREC_BF16X6_UPDATE = 0, 1, 2, 3
 IBMI_INIT_IDENTITY, IBMI_INIT_BLOCKDIAG_INV, IBMI_INIT_GIVEN = 0, 1, 2
-IBMI_STOP_FRO, IBMI_STOP_REL_BOUND, IBMI_STOP_REL_HR = 0, 1, 2
+IBMI_STOP_FRO, IBMI_STOP_REL_BOUND, IBMI_STOP_REL_HR, IBMI_STOP_PAPER = 0, 1, 2, 3
 
 _INIT = {"identity": IBMI_INIT_IDENTITY, "blockdiag_inv": IBMI_INIT_BLOCKDIAG_INV,
          "given": IBMI_INIT_GIVEN}
-_STOP = {"fro": IBMI_STOP_FRO, "rel_bound": IBMI_STOP_REL_BOUND, "rel_hr": IBMI_STOP_REL_HR}
+_STOP = {"fro": IBMI_STOP_FRO, "rel_bound": IBMI_STOP_REL_BOUND, "rel_hr": IBMI_STOP_REL_HR,
+         "paper": IBMI_STOP_PAPER}
 _PREC = {"fp64": IBMI_PREC_FP64, "fp32": IBMI_PREC_FP32_UPDATE, "bf16x3": IBMI_PREC_BF16X3_UPDATE,
          "bf16x6": IBMI_PREC_BF16X6_UPDATE}
 

@@ -109,7 +109,7 @@ ibmi_status check_options(const ibmi_options* o) {
   if (o->precision < IBMI_PREC_FP64 || o->precision > IBMI_PREC_BF16X6_UPDATE)
     return IBMI_ERR_INVALID_ARG;
   if (o->init < IBMI_INIT_IDENTITY || o->init > IBMI_INIT_GIVEN) return IBMI_ERR_INVALID_ARG;
-  if (o->stop < IBMI_STOP_FRO || o->stop > IBMI_STOP_REL_HR) return IBMI_ERR_INVALID_ARG;
+  if (o->stop < IBMI_STOP_FRO || o->stop > IBMI_STOP_PAPER) return IBMI_ERR_INVALID_ARG;
   if (o->stop == IBMI_STOP_REL_BOUND && !(o->lambda_min > 0.0)) return IBMI_ERR_INVALID_ARG;
   return IBMI_OK;
 }
@@ -124,16 +124,16 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
 // Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel 96x64
 // tiles (six row tiles cover a 576-row set; 0.76 of the FP64 peak against 0.71 for 64x64),
 // the diagonal product 64x64 tiles with many resident waves, the square residual the
-// 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 96x128 tiles
-// (two terms) or 6-wave 192x128 tiles (three terms) with K cut into chunks of 2048 (the few
-// row tiles of a 576-row set times eight chunks fill the chip where whole-K tiles leave it
-// half idle).
+// 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 8-wave
+// 192x256 tiles (two terms; with three terms they would not fit in LDS) or 6-wave 192x128
+// tiles (three terms), K cut into chunks of 2048 (the three row tiles of a 576-row set times
+// eight chunks fill the chip where whole-K tiles leave it half idle).
 struct Tuning {
   GemmCfg panel = ibmi::GEMM_64x64_K16, diag = ibmi::GEMM_64x64_K16,
           resid = ibmi::GEMM_128x128_W8, plan = ibmi::GEMM_64x64_K16, upd32 = ibmi::GEMM_64x64,
           small = ibmi::GEMM_64x64_K16;
   int diag_splits = 0;  // 0 = automatic
-  SplitCfg split = ibmi::SPLIT_96x128;   // split-bfloat16 update product, two terms
+  SplitCfg split = ibmi::SPLIT_192x256;  // split-bfloat16 update product, two terms
   SplitCfg split6 = ibmi::SPLIT_192x128; // the same with three terms
   int64_t split_kchunk = 2048;           // their K chunk (0: whole K per tile)
 };
@@ -670,6 +670,27 @@ static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, boo
   return IBMI_OK;
 }
 
+// ||(H A)[I_K, I_K^c]||_F^2 for the last set: rows s.. of H (H symmetric, so the product's
+// row operand is H's columns s..) times A's columns on the two-segment complement.
+static ibmi_status paper_sq(ibmi_plan_t P, const double* dH, int64_t ldh, double* out) {
+  hipStream_t st = P->st;
+  const int K = (int)P->s.size();
+  const BlockDesc& d = P->L.blocks[K - 1];
+  const int64_t c = P->p - d.b;
+  if (c == 0) {
+    *out = 0.0;
+    return IBMI_OK;
+  }
+  Opnd Xh{dH, ldh, IdxMap{}, IdxMap{d.s, INT64_MAX, 0}};
+  Opnd Ya{P->A, P->lda, IdxMap{}, IdxMap{0, d.s, d.b}};
+  int64_t n_red = 0;
+  IBMI_HIP(ibmi::gemm_sumsq(P->t.resid, Xh, Ya, d.b, c, P->p, P->red(), &n_red, st));
+  IBMI_HIP(ibmi::reduce_sum(P->red(), n_red, P->scal() + 3, st));
+  IBMI_HIP(hipMemcpyAsync(out, P->scal() + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+  IBMI_HIP(hipStreamSynchronize(st));
+  return IBMI_OK;
+}
+
 // ||H R||_F^2 with R = I - A H as stored by the last residual evaluation (H symmetric, so
 // the product's row operand H^T is H itself).
 static ibmi_status hr_sq(ibmi_plan_t P, const double* dH, int64_t ldh, double* out) {
@@ -721,6 +742,11 @@ ibmi_status ibmi_solve(ibmi_plan_t plan, double* dH, int64_t ldh, ibmi_info* inf
     double sv = rho;
     if (o.stop == IBMI_STOP_REL_BOUND) {
       sv = rho / (o.lambda_min * std::sqrt(h2));
+    } else if (o.stop == IBMI_STOP_PAPER) {
+      double e2 = 0.0;
+      rc = paper_sq(plan, dH, ldh, &e2);
+      if (rc != IBMI_OK) return rc;
+      sv = std::sqrt(e2);
     } else if (o.stop == IBMI_STOP_REL_HR) {
       const bool last = o.fixed_sweeps > 0 && info->sweeps >= limit;
       const bool due = rho < 1.0 && (ratio < 0.0 || ratio * rho < o.tol || rho < 0.1 * rho_eval);

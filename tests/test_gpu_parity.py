@@ -81,6 +81,29 @@ def test_ragged_random_spd(ib, p, b, ovl, seed):
     _compare(ib, A, oracle.partition(p, b, ovl), 3)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_branch_free_path_with_edge_tiles(ib, precision):
+    """Sets of 272 rows at p = 1040: every K range (c = 768, p = 1040) is a whole number of
+    stages, so the products take the branch-free loop, while 272 rows and 1040 columns leave
+    partial edge tiles that load the last valid columns in place of missing ones."""
+    _say(f"branch-free path with edge tiles p=1040 b=272 ({precision})")
+    A = workloads.wishart_spd(1040, np.random.default_rng(21), shift=0.3)
+    ranges = [(0, 272), (256, 528), (512, 784), (768, 1040)]
+    if precision == "fp64":
+        _compare(ib, A, ranges, 3)
+        return
+    bp = oracle.plan(A, ranges)
+    h_emul, h64 = np.eye(1040), np.eye(1040)
+    for _ in range(2):
+        oracle.correction_sweep(A, h_emul, bp, precision)
+        oracle.correction_sweep(A, h64, bp, "fp64")
+    out, H = _gpu_solve(ib, A, bounds=ranges, precision=precision, tol=1e-300, fixed_sweeps=2)
+    assert np.array_equal(H, H.T)
+    # A wrong edge load corrupts outputs at O(1); the split rounding itself is ~1e-6 here and
+    # FP32 accumulation order moves the result by about a third of that (CPU emulation).
+    assert _rel(H, h_emul) < 2.0 * _rel(h_emul, h64)
+
+
 def test_odd_explicit_bounds(ib):
     _say("explicit odd bounds p=151")
     A = workloads.wishart_spd(151, np.random.default_rng(9), shift=0.3)
@@ -308,6 +331,20 @@ def test_rel_hr_stop_matches_oracle(ib, form):
         assert _rel(H, ref.h) <= TOL
     else:
         assert abs(out.sweeps - ref.sweeps) <= 2
+
+
+def test_paper_stop_matches_oracle(ib):
+    """Stop on the Frobenius form of the paper's eq. (error) estimate for the last set: same
+    stopping sweep and stop value as the oracle, and the same H."""
+    _say("paper estimate stop p=700, tol 1e-8")
+    A = workloads.wishart_spd(700, np.random.default_rng(14), shift=0.3)
+    ranges = oracle.partition(700, 200, 24)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-8, stop="paper", max_sweeps=300)
+    out, H = _gpu_solve(ib, A, bounds=ranges, tol=1e-8, stop="paper", max_sweeps=300)
+    assert ref.converged and out.converged and out.sweeps == ref.sweeps
+    # both sides evaluate the block with FP64 rounding of their own order
+    assert out.stop_value == pytest.approx(ref.stop_value, rel=1e-4)
+    assert _rel(H, ref.h) <= TOL
 
 
 def test_sweep_entry_point_matches_solve(ib):

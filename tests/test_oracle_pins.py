@@ -459,3 +459,21 @@ def test_rel_hr_stop_ends_at_the_true_error():
     assert 1 <= res.evaluations <= 10 and res.evaluations < res.sweeps
     prev = oracle.ibmi_solve(A, ranges, tol=1e-300, fixed_sweeps=res.sweeps - 1)
     assert _rel(prev.h, inv) > 0.5 * tol
+
+
+def test_paper_estimate_frobenius_form():
+    """The Frobenius form of eq. (error) is the Frobenius norm of the (1,2) block of H A (the
+    two-term expression is that block split over I and I^c), bounds the paper's spectral
+    form from above, and vanishes at A^{-1}; the "paper" stop test ends a solve on it."""
+    A = workloads.wishart_spd(300, np.random.default_rng(4), shift=0.3)
+    ranges = oracle.partition(300, 100, 20)
+    res = oracle.ibmi_solve(A, ranges, tol=1e-300, fixed_sweeps=3)
+    idx = np.arange(*ranges[-1])
+    ic = np.setdiff1d(np.arange(300), idx)
+    fro = oracle.paper_error(A, res.h, idx, "fro")
+    assert fro == pytest.approx(np.linalg.norm((res.h @ A)[np.ix_(idx, ic)]), rel=1e-10)
+    assert fro >= oracle.paper_error(A, res.h, idx) * (1 - 1e-12)
+    assert oracle.paper_error(A, np.linalg.inv(A), idx, "fro") < 1e-10
+    sol = oracle.ibmi_solve(A, ranges, tol=1e-8, stop="paper", max_sweeps=200)
+    assert sol.converged and sol.stop_value < 1e-8
+    assert oracle.paper_error(A, sol.h, idx, "fro") == pytest.approx(sol.stop_value, rel=1e-12)
