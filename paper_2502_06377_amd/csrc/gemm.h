@@ -57,8 +57,9 @@ template <> struct Mfma<float> {
 // Workgroup tile BM x BN, K staged BK at a time through LDS (double buffered: global loads
 // for stage t+1 are in flight while stage t feeds the matrix cores).  WM x WN waves, each
 // owning a (BM/WM) x (BN/WN) block of 16x16 MFMA tiles; every tile is an independent
-// accumulation chain, and a wave needs about 8 of them in flight to keep the FP64 matrix
-// pipe busy (a measured property of gfx950: 4 chains per wave reach ~60% of peak).
+// accumulation chain (on gfx950 two chains per wave with 4 waves per SIMD already keep the
+// FP64 matrix pipe at 99% of peak in an MFMA-only measurement, so resident waves matter
+// more than chains per wave).
 // Operand tiles sit in LDS as they sit in memory ([k][x], x contiguous), which is also the
 // order the MFMA fragments are read in: lane l takes X(k0 + l/16, x0 + l%16), so each
 // ds_read touches 4 rows of 16 consecutive elements.
@@ -69,18 +70,19 @@ template <> struct Mfma<float> {
 // operand panels in that XCD's L2.
 // ---------------------------------------------------------------------------------------
 // LDS of one tile configuration, declared in a function that does not depend on the
-// epilogue (a kernel running the tile code with two epilogues would hold one copy).  FP32 fragments read 16 consecutive 4-byte words from 4 rows per instruction;
-// padding each row by 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left
-// unpadded (no bank conflicts measured).
-template <typename T, int BM, int BN, int BK, int NW>
+// epilogue (a kernel running the tile code with two epilogues holds one copy).  FP32
+// fragments read 16 consecutive 4-byte words from 4 rows per instruction; padding each row by
+// 64 bytes puts the 4 rows on different LDS banks.  FP64 rows are left unpadded (no bank
+// conflicts measured).
+template <typename T, int BM, int BN, int BK>
 struct GemmSmem {
   static constexpr int PAD = sizeof(T) == 4 ? 16 : 0;
   T Xs[2][BK][BM + PAD];
   T Ys[2][BK][BN + PAD];
 };
-template <typename T, int BM, int BN, int BK, int NW>
-__device__ __forceinline__ GemmSmem<T, BM, BN, BK, NW>& gemm_smem() {
-  __shared__ __attribute__((aligned(16))) GemmSmem<T, BM, BN, BK, NW> sm;
+template <typename T, int BM, int BN, int BK>
+__device__ __forceinline__ GemmSmem<T, BM, BN, BK>& gemm_smem() {
+  __shared__ __attribute__((aligned(16))) GemmSmem<T, BM, BN, BK> sm;
   return sm;
 }
 
@@ -115,7 +117,7 @@ __device__ __forceinline__ void gemm_tile(const Opnd& X, const Opnd& Y, int64_t 
   static_assert(XV * VEC == XE && YV * VEC == YE && BM % VEC == 0 && BN % VEC == 0, "bad VEC");
   static_assert(TM * 16 == WTM && TN * 16 == WTN && BK % 4 == 0, "bad wave tile");
 
-  auto& sm = gemm_smem<T, BM, BN, BK, NT / 64>();
+  auto& sm = gemm_smem<T, BM, BN, BK>();
   auto& Xs = sm.Xs;
   auto& Ys = sm.Ys;
   // The per-wave partial sums of the residual epilogues reuse the operand buffers: they are
