@@ -197,9 +197,11 @@ ibmi_status ibmi_residual(ibmi_plan_t plan, const double* dH, int64_t ldh, doubl
 /* Kernel timing, for measurement.  While enabled, launches are bracketed by HIP events on the
  * plan's stream in three categories.  FP64 form: 0 = panel GEMM V = W H[I^c,I^c] with its
  * scatter into H (2 b c^2 flops), 1 = diagonal update (split-K W H[I^c,I] and H[I,I];
- * 2 b^2 c), 2 = residual (2 p^3).  FP32-update form: 0 = the FP32 product A[:,I]^T D
- * (2 b (u p + (p-u) u) flops, u = rows already updated in the sweep), 1 = the FP64
- * corrections of the set (4 b^2 c + 2 b^3), 2 = residual with its store (2 p^3).
+ * 2 b^2 c), 2 = residual (2 p^3).  Low-precision forms: 0 = the update product
+ * R[I,:] - A[I,:] D in FP32 or split bfloat16 (2 b (u p + (p-u) u) FP32-level flops, u = rows
+ * already updated in the sweep; the split forms' partial-sum pass included), 1 = the FP64
+ * corrections of the set (4 b^2 c + 2 b^3), 2 = residual with its store (2 p^3).  The
+ * REL_HR and PAPER stop evaluations are not timed.
  * ibmi_kernel_times synchronises the stream, then returns and resets, per category:
  * accumulated milliseconds, launch counts and flops.  Host arrays of length 3; any may be NULL. */
 ibmi_status ibmi_set_profiling(ibmi_plan_t plan, int32_t on);
