@@ -347,6 +347,20 @@ def test_paper_stop_matches_oracle(ib):
     assert _rel(H, ref.h) <= TOL
 
 
+def test_stagnation_guard_matches_oracle(ib):
+    """A tolerance below the FP64 floor: both sides stop with floor_limited, within a few
+    sweeps of each other (where the floor is first touched depends on rounding noise), and
+    the GPU's best residual is at the oracle's floor level."""
+    _say("stagnation guard p=1500 Matern-3/2, tol 1e-11 (floor ~3e-10)")
+    A = workloads.config2_matrix(p=1500)
+    ranges = oracle.partition(1500, 576, 64)
+    ref = oracle.ibmi_solve(A, ranges, tol=1e-11, max_sweeps=500)
+    out, H = _gpu_solve(ib, A, bounds=ranges, tol=1e-11, max_sweeps=500)
+    assert ref.floor_limited and out.floor_limited and not out.converged
+    assert abs(out.sweeps - ref.sweeps) <= 4, (out.sweeps, ref.sweeps)
+    assert min(out.history) < 3 * min(ref.history)
+
+
 def test_sweep_entry_point_matches_solve(ib):
     _say("ibmi_sweep vs ibmi_solve p=640")
     A = workloads.config2_matrix(p=640)
