@@ -76,3 +76,35 @@ def test_status_strings(binding):
     assert binding.ibmi_status_str(0) == "IBMI_OK"
     assert binding.ibmi_status_str(2) == "IBMI_ERR_NOT_SPD"
     assert binding.ibmi_status_str(99) == "IBMI_UNKNOWN_STATUS"
+
+
+def test_workspace_bytes_per_form_and_stop(binding):
+    """The low-precision forms add their FP32 copies of A and D (p x ld32, ld32 = p rounded
+    up to 4) and R (p x p FP64); the split forms also their K-chunk partials; the REL_HR stop
+    adds R to the FP64 form; precisions and stop tests outside the enums are rejected."""
+    m = binding
+    p = 1001
+    base = m.ibmi_workspace_bytes(m.make_options(p, 256, 32))
+    ld32 = (p + 3) // 4 * 4
+    for form in ("fp32", "bf16x3", "bf16x6"):
+        n = m.ibmi_workspace_bytes(m.make_options(p, 256, 32, precision=form))
+        assert n >= base + 2 * p * ld32 * 4 + p * p * 8, form
+    assert m.ibmi_workspace_bytes(m.make_options(p, 256, 32, stop="rel_hr")) >= base + p * p * 8
+    assert m.ibmi_workspace_bytes(m.make_options(p, 256, 32, stop="paper")) == base
+    o = m.make_options(p, 256, 32)
+    o.precision = 4
+    assert m.ibmi_workspace_bytes(o) == 0
+    o = m.make_options(p, 256, 32)
+    o.stop = 4
+    assert m.ibmi_workspace_bytes(o) == 0
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: asked for more it exits with status 2 and says why."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
