@@ -31,7 +31,7 @@ PANEL_KERNEL = "gemm_kernel<double, 96, 64, 16, 2, 2, 1, 2, true>"
 # used, matrix-core products executed per FP32-level product, instruction type, kernel).
 UPDATE_KERNELS = {
     "fp32": (157.3, 1, "f32",
-             "gemm_kernel<float, 64, 64, 32, 2, 2, 5, 4, true> (R[I,:] - A[I,:] D)"),
+             "gemm_kernel<float, 96, 128, 32, 2, 2, 5, 4, true> (R[I,:] - A[I,:] D)"),
     "bf16x3": (2500.0, 3, "bf16",
                "split_gemm_kernel<192, 256, 32, 2, 4, 2, true> (R[I,:] - A[I,:] D)"),
     "bf16x6": (2500.0, 6, "bf16",

@@ -123,11 +123,11 @@ GemmCfg env_cfg(const char* name, GemmCfg dflt) {
 
 // Defaults measured on MI355X at p = 16384 (sweep of all configurations): the panel 96x64
 // tiles (six row tiles cover a 576-row set; 0.76 of the FP64 peak against 0.71 for 64x64),
-// the diagonal product 64x64 tiles with many resident waves, the square residual the
-// 8-wave 128x128 tile, the FP32 update the 64x64 tile, the split-bfloat16 update 8-wave
-// 192x256 tiles (two terms; with three terms they would not fit in LDS) or 6-wave 192x128
-// tiles (three terms), K cut into chunks of 2048 (the three row tiles of a 576-row set times
-// eight chunks fill the chip where whole-K tiles leave it half idle).
+// the diagonal product 64x64 tiles with many resident waves, the square residual the 8-wave
+// 128x128 tile, the FP32 update 96x128 tiles (64x64 below p = 8192), the split-bfloat16
+// update 8-wave 192x256 tiles (two terms; with three terms they would not fit in LDS) or
+// 6-wave 192x128 tiles (three terms), K cut into chunks of 2048 (the three row tiles of a
+// 576-row set times eight chunks fill the chip where whole-K tiles leave it half idle).
 struct Tuning {
   GemmCfg panel = ibmi::GEMM_64x64_K16, diag = ibmi::GEMM_64x64_K16,
           resid = ibmi::GEMM_128x128_W8, plan = ibmi::GEMM_64x64_K16, upd32 = ibmi::GEMM_64x64,
@@ -143,7 +143,10 @@ Tuning tuning_for(int64_t p) {
   if (p < 2048) {  // small matrices: more, smaller tiles
     t.resid = ibmi::GEMM_64x64_K16;
   }
-  if (p >= 8192) t.panel = ibmi::GEMM_96x64_K16;  // enough column tiles to fill the chip
+  if (p >= 8192) {  // enough column tiles to fill the chip with the larger tiles
+    t.panel = ibmi::GEMM_96x64_K16;
+    t.upd32 = ibmi::GEMM_96x128;
+  }
   t.upd32 = env_cfg("IBMI_CFG_UPD32", t.upd32);
   t.panel = env_cfg("IBMI_CFG_PANEL", t.panel);
   t.diag = env_cfg("IBMI_CFG_DIAG", t.diag);
@@ -187,7 +190,7 @@ int diag_splits_for(int64_t b, int64_t c, GemmCfg cfg, int forced) {
 struct Layout {
   size_t desc = 0, fac = 0, wt = 0, part = 0, red = 0, red2 = 0, scal = 0, status = 0, total = 0;
   // Correction (FP32 / split-bfloat16 update) forms only (zero size otherwise)
-  size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, x2 = 0, spart = 0;
+  size_t a32 = 0, dmat = 0, rt = 0, rkt = 0, delta = 0, tt = 0, spart = 0;
   int64_t ld32 = 0;  // row stride of the FP32 copies of A and D (multiple of 4)
   std::vector<BlockDesc> blocks;
   std::vector<int64_t> wt_off;  // doubles, relative to wt
@@ -254,8 +257,6 @@ Layout make_layout(const ibmi_options* o, const std::vector<int64_t>& s,
     L.delta = off;
     off = align_up(off + (size_t)std::max<int64_t>(c_max, 1) * L.b_max * 8);
     L.tt = off;
-    off = align_up(off + (size_t)L.b_max * L.b_max * 8);
-    L.x2 = off;
     off = align_up(off + (size_t)L.b_max * L.b_max * 8);
     if (o->precision != IBMI_PREC_FP32_UPDATE) {
       const int64_t chunks = ibmi::split_max_chunks(p, t.split_kchunk);
@@ -348,7 +349,6 @@ struct ibmi_plan_s {
   double* rkt() const { return (double*)(work + L.rkt); }
   double* delta() const { return (double*)(work + L.delta); }
   double* tt() const { return (double*)(work + L.tt); }
-  double* x2() const { return (double*)(work + L.x2); }
 };
 
 extern "C" {
@@ -576,8 +576,11 @@ static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int 
   IBMI_HIP(ibmi::gemm_partial(P->t.diag, Xd, Ya, b, b, c, splits, P->part(), st));
   IBMI_HIP(ibmi::corr_diag(P->rkt(), p, s, P->part(), splits, b, P->tt(), st));
   Opnd Xt{P->tt(), b, IdxMap{}, IdxMap{}};
-  IBMI_HIP(ibmi::gemm_store(P->t.small, Xt, Yi, b, b, b, P->x2(), b, st));
-  IBMI_HIP(ibmi::corr_apply(P->x2(), b, dH, ldh, P->dmat(), ld32, s, st));
+  // (R[I,I] - Delta^T A[I^c,I]) A_I^{-1}, split over K like the diagonal product (the split
+  // buffer is free again once corr_diag has read it): 81 tiles alone leave most CUs idle.
+  const int s2 = std::min<int>(P->L.splits, (int)std::max<int64_t>(1, b / 64));
+  IBMI_HIP(ibmi::gemm_partial(P->t.small, Xt, Yi, b, b, b, s2, P->part(), st));
+  IBMI_HIP(ibmi::corr_apply(P->part(), s2, b, dH, ldh, P->dmat(), ld32, s, st));
   prof_end(P, 1, ev, 4.0 * (double)b * b * c + 2.0 * (double)b * b * b);
   return IBMI_OK;
 }

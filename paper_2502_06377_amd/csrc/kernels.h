@@ -174,8 +174,10 @@ hipError_t to_f32(const double* a, int64_t lda, float* out, int64_t ldo, int64_t
 hipError_t zero_f32(float* x, int64_t n, hipStream_t st);
 hipError_t corr_diag(const double* rkt, int64_t ldr, int64_t s, const double* part, int splits,
                      int64_t b, double* tt, hipStream_t st);
-hipError_t corr_apply(const double* x, int64_t b, double* H, int64_t ldh, float* D, int64_t ldd,
-                      int64_t s, hipStream_t st);
+// X = sum of `splits` partial b x b products (fixed order); H[s+i][s+j] += (X[i][j] +
+// X[j][i]) / 2 and the same increment, rounded to FP32, into D.
+hipError_t corr_apply(const double* part, int splits, int64_t b, double* H, int64_t ldh, float* D,
+                      int64_t ldd, int64_t s, hipStream_t st);
 
 // Grouped launch of tasks[0..ntasks) (tile prefix sums in tile_off, total_tiles workgroups);
 // tasks of matrices with active[mat] == 0 are skipped when active is non-null.

@@ -349,24 +349,32 @@ hipError_t corr_diag(const double* rkt, int64_t ldr, int64_t s, const double* pa
   return hipGetLastError();
 }
 
-// H[s+i][s+j] += (X[i][j] + X[j][i]) / 2 and the same increment (rounded) into D.
-__global__ void corr_apply_kernel(const double* x, int64_t b, double* H, int64_t ldh, float* D,
-                                  int64_t ldd, int64_t s) {
+// X = sum of the split-K partials in order; H[s+i][s+j] += (X[i][j] + X[j][i]) / 2 and the
+// same increment (rounded) into D.  Both sums run in the same order, so the increment, and H,
+// stay bitwise symmetric.
+__global__ void corr_apply_kernel(const double* part, int splits, int64_t b, double* H,
+                                  int64_t ldh, float* D, int64_t ldd, int64_t s) {
   const int64_t n = b * b;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / b, j = e % b;
-    const double inc = 0.5 * (x[e] + x[j * b + i]);
+    double xij = 0.0, xji = 0.0;
+    for (int z = 0; z < splits; ++z) {
+      xij += part[z * n + e];
+      xji += part[z * n + j * b + i];
+    }
+    const double inc = 0.5 * (xij + xji);
     H[(s + i) * ldh + s + j] += inc;
     D[(s + i) * ldd + s + j] += (float)inc;
   }
 }
 
-hipError_t corr_apply(const double* x, int64_t b, double* H, int64_t ldh, float* D, int64_t ldd,
-                      int64_t s, hipStream_t st) {
+hipError_t corr_apply(const double* part, int splits, int64_t b, double* H, int64_t ldh, float* D,
+                      int64_t ldd, int64_t s, hipStream_t st) {
   const int64_t n = b * b;
   const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(corr_apply_kernel, dim3(grid), dim3(256), 0, st, x, b, H, ldh, D, ldd, s);
+  hipLaunchKernelGGL(corr_apply_kernel, dim3(grid), dim3(256), 0, st, part, splits, b, H, ldh, D,
+                     ldd, s);
   return hipGetLastError();
 }
 
