@@ -108,3 +108,17 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_covariance_row_chunks_same_bits():
+    """The chunked covariance generator (used where the matrix is too large to build on the
+    host at once) yields exactly the rows of the full matrix, nugget included."""
+    import numpy as np
+    import workloads
+    pts = workloads.sorted_points(1500, 2, np.random.default_rng(2))
+    full = workloads.covariance(pts, "matern32", 0.1, 1e-2)
+    out = np.full_like(full, np.nan)
+    for r0, r1, rows in workloads.covariance_row_chunks(pts, "matern32", 0.1, 1e-2,
+                                                         row_chunk=333):
+        out[r0:r1] = rows
+    assert np.array_equal(out, full)

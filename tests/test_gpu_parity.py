@@ -236,6 +236,52 @@ def test_full_size_16384_first_block_and_properties(ib):
     plan.close()
 
 
+def test_max_size_past_int32_element_count(ib):
+    """p = 46400, so p^2 exceeds 2^31 - 1 and every flat index of A, H and the workspace must
+    be 64-bit (the largest benchmark matrix has p^2 = 2.7e8).  Matern-3/2 (workload 2's
+    kernel) on seeded points, built in row chunks straight into device memory.  After block
+    step 0 from H = I the rows of set 0 match the oracle's (eq. (IBMI) with H_{I^c} = I);
+    after the full sweep H is bitwise symmetric on sampled rows, (I - H A)[:, I_K] = 0 on
+    sampled columns of the last set, and the residual is finite."""
+    p = 46400
+    assert p * p > 2 ** 31 - 1
+    _say(f"max size p={p}: block 0 vs oracle, sweep properties")
+    pts = workloads.sorted_points(p, 2, np.random.default_rng(2))
+    A = torch.empty((p, p), dtype=torch.float64, device="cuda")
+    ranges = oracle.partition(p, 576, 64)
+    s0, e0 = ranges[0]
+    a_host = np.empty((p, p))  # only rows of set 0 are filled (pages of the rest untouched)
+    for r0, r1, rows in workloads.covariance_row_chunks(pts, "matern32", 0.1, 1e-2):
+        A[r0:r1].copy_(torch.from_numpy(rows))
+        if r0 < e0:
+            a_host[r0:min(r1, e0)] = rows[:min(r1, e0) - r0]
+    plan = ib.Plan(A, block_rows=576, overlap=64)
+    assert plan.blocks == ranges
+    H = torch.empty((p, p), dtype=torch.float64, device="cuda")
+    ib.ibmi_init_h(plan.handle, H)
+    ib.ibmi_block_step(plan.handle, H, 0)
+    torch.cuda.synchronize()
+    bp = oracle.block_factors(a_host, s0, e0)
+    del a_host
+    rows = H[s0:e0].cpu().numpy()
+    assert _rel(rows[:, bp.comp], -bp.w) <= TOL
+    assert _rel(rows[:, bp.idx], bp.ainv + bp.w @ bp.w.T) <= TOL
+    for k in range(1, len(ranges)):
+        ib.ibmi_block_step(plan.handle, H, k)
+    torch.cuda.synchronize()
+    assert torch.equal(H[::997], H[:, ::997].T)
+    s, e = ranges[-1]
+    cols = torch.arange(s, e, 61, device="cuda")
+    eye = torch.zeros((p, cols.numel()), dtype=torch.float64, device="cuda")
+    eye[cols, torch.arange(cols.numel(), device="cuda")] = 1.0
+    R = eye - H @ A[:, cols].contiguous()
+    bound = 1e-12 * H.abs().max().item() * A.abs().max().item() * p
+    assert R.abs().max().item() < bound
+    res = plan.residual(H)
+    assert np.isfinite(res) and res > 0
+    plan.close()
+
+
 # ------------------------------------------------------------ low-precision update forms
 
 MIXED = ["fp32", "bf16x3", "bf16x6"]

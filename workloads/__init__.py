@@ -22,7 +22,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "sorted_points", "pairwise_distance", "kernel_matrix", "covariance",
+    "sorted_points", "pairwise_distance", "kernel_matrix", "covariance", "covariance_row_chunks",
     "config1_matrix", "config2_matrix", "config3_matrix", "config4_batch",
     "config5_arrivals", "request_matrix", "wishart_spd", "CONFIGS", "Workload", "Request",
 ]
@@ -77,6 +77,18 @@ def kernel_matrix(pts: np.ndarray, kind: str, ell: float, variance: float = 1.0,
         r1 = min(n, r0 + row_chunk)
         out[r0:r1] = _kernel_of_distance(pairwise_distance(pts[r0:r1], pts), kind, ell, variance)
     return out
+
+
+def covariance_row_chunks(pts: np.ndarray, kind: str, ell: float, nugget: float,
+                          variance: float = 1.0, row_chunk: int = 2048):
+    """The rows of ``covariance(pts, ...)`` in chunks: yields (r0, r1, rows r0..r1-1), the
+    same bits as the full matrix, for matrices too large to hold on the host at once."""
+    n = pts.shape[0]
+    for r0 in range(0, n, row_chunk):
+        r1 = min(n, r0 + row_chunk)
+        rows = _kernel_of_distance(pairwise_distance(pts[r0:r1], pts), kind, ell, variance)
+        rows[np.arange(r1 - r0), np.arange(r0, r1)] += nugget
+        yield r0, r1, rows
 
 
 def covariance(pts: np.ndarray, kind: str, ell: float, nugget: float,
