@@ -307,6 +307,11 @@ def emulate_product(x: np.ndarray, y: np.ndarray, kind: str) -> np.ndarray:
     Heinecke, ARITH 2019).  ``bf16x6``: three-term split hi + mid + lo, keeping the six
     products whose term indices sum to at most 2.  Each bf16 x bf16 product is exact in
     FP32, so the FP32 GEMM over the split terms models the hardware's accumulation.
+
+    Pinned by hand-computed products whose dropped and kept pairs are known exactly, by the
+    split's error bound on random operands (with every result an FP32 number), and, for the
+    bfloat16 rounding, by a brute-force rational round-to-nearest-even and the library's own
+    float32 -> bfloat16 conversion.
     """
     if kind == "fp64":
         return x @ y

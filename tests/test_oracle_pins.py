@@ -383,6 +383,87 @@ def test_fp32_correction_form_refines_to_fp64_accuracy():
     assert _rel(H, ref) < 1e-10
 
 
+def _bf16_nearest_even(v: float) -> float:
+    """Brute force: the two bfloat16 neighbours of a finite float32 v (8 significant bits)
+    by exact rational arithmetic, the nearer one, ties to the even significand."""
+    from fractions import Fraction
+    if v == 0.0:
+        return v
+    f = Fraction(v)
+    e = math.floor(math.log2(abs(v)))
+    while Fraction(2) ** e > abs(f):
+        e -= 1
+    while Fraction(2) ** (e + 1) <= abs(f):
+        e += 1
+    ulp = Fraction(2) ** (e - 7)
+    lo = (abs(f) // ulp) * ulp
+    hi = lo + ulp
+    d_lo, d_hi = abs(f) - lo, hi - abs(f)
+    if d_lo < d_hi or (d_lo == d_hi and (lo / ulp) % 2 == 0):
+        r = lo
+    else:
+        r = hi
+    return float(r if f > 0 else -r)
+
+
+def test_bf16_rounding_nearest_even():
+    """The oracle's float32 -> bfloat16 rounding is round to nearest, ties to even: against
+    a brute-force rational rounding and the library conversion on random and tie cases."""
+    import torch
+    from oracle.ibmi import _round_bf16
+    rng = np.random.default_rng(30)
+    x = (rng.standard_normal(2000) * np.exp2(rng.integers(-30, 30, 2000))).astype(np.float32)
+    # exact ties: 8 significant bits plus a half unit in the last place
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 3 * 2.0 ** -9 + 2.0 ** -16,
+                     1 + 2.0 ** -8 + 2.0 ** -20, 1.0, 1.5, 2.0 ** -10], dtype=np.float32)
+    x = np.concatenate([x, ties])
+    got = _round_bf16(x)
+    want = np.array([_bf16_nearest_even(float(v)) for v in x], dtype=np.float32)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, torch.from_numpy(x).to(torch.bfloat16).float().numpy())
+    assert got[-8] == 1.0 and got[-7] == 1 + 2.0 ** -6 and got[-4] == 1 + 2.0 ** -7
+
+
+def test_split_products_closed_forms():
+    """Hand-computed cases of the emulated low-precision products.  x = 1 + 2^-10 splits as
+    hi = 1, lo = 2^-10: bf16x3 keeps hi*hi + 2 hi*lo = 1 + 2^-9 and drops lo*lo = 2^-20;
+    bf16x6 keeps it (three terms, pair (1,1)), so it returns x^2 exactly; FP32 rounds x^2 =
+    1 + 2^-9 + 2^-20 exactly too (21 bits).  Sums run in FP32: 1 + 2^-30 accumulates to 1."""
+    x = np.array([[1 + 2.0 ** -10]])
+    assert oracle.emulate_product(x, x, "bf16x3")[0, 0] == 1 + 2.0 ** -9
+    assert oracle.emulate_product(x, x, "bf16x6")[0, 0] == (1 + 2.0 ** -10) ** 2
+    assert oracle.emulate_product(x, x, "fp32")[0, 0] == (1 + 2.0 ** -10) ** 2
+    row, col = np.array([[1.0, 2.0 ** -30]]), np.array([[1.0], [1.0]])
+    for kind in ("fp32", "bf16x3", "bf16x6"):
+        assert oracle.emulate_product(row, col, kind)[0, 0] == 1.0
+    assert oracle.emulate_product(row, col, "fp64")[0, 0] == 1 + 2.0 ** -30
+    # a second term that needs the third split term: hi = 1, mid = 2^-9, lo = 2^-17
+    y = np.array([[1 + 2.0 ** -9 + 2.0 ** -17]])
+    one = np.array([[1.0]])
+    assert oracle.emulate_product(y, one, "bf16x3")[0, 0] == 1 + 2.0 ** -9
+    assert oracle.emulate_product(y, one, "bf16x6")[0, 0] == 1 + 2.0 ** -9 + 2.0 ** -17
+
+
+@pytest.mark.parametrize("kind,u", [("bf16x3", 2.0 ** -16), ("bf16x6", 2.0 ** -23)])
+def test_split_products_within_their_error_bound(kind, u):
+    """On random operands each emulated entry lies within the split's bound of the FP64
+    product: per term the dropped pairs are below 3u |x||y| (two operands, each term split
+    to relative 2^-8 per term), and the FP32 sum over n terms adds at most n 2^-24 |x||y|."""
+    rng = np.random.default_rng(31)
+    n = 200
+    x, y = rng.standard_normal((30, n)), rng.standard_normal((n, 20))
+    got = oracle.emulate_product(x, y, kind)
+    scale = np.abs(x) @ np.abs(y)
+    assert np.all(np.abs(got - x @ y) <= (3 * u + n * 2.0 ** -24) * scale)
+    # FP32 accumulation: every entry is an FP32 number
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+    # the kept pairs matter: the leading bfloat16 terms alone are far off
+    from oracle.ibmi import _round_bf16
+    hx = _round_bf16(x.astype(np.float32)).astype(np.float64)
+    hy = _round_bf16(y.astype(np.float32)).astype(np.float64)
+    assert np.abs(got - x @ y).max() < 0.01 * np.abs(hx @ hy - x @ y).max()
+
+
 def test_stagnation_guard_stops_at_the_floor():
     """A tolerance below the FP64 floor of ||I - A H||_F ends with floor_limited, not at the
     cap; the same matrix with a reachable tolerance converges."""
