@@ -80,11 +80,12 @@ def cpu_baseline(A, ranges, n_sets):
                       f"sweep 1 from H = I at p={p} (FP64 NumPy/OpenBLAS), {dt:.1f} s"}
 
 
-def batched_bench(ib, torch, oracle):
+def batched_bench(ib, torch):
     """256 Wishart matrices (p log-uniform in [128, 2048]), b = 128, overlap 16, tol 1e-8,
     solved as one batch: cached/autotuned tile shapes, then a timed solve."""
     import workloads
     from paper_2502_06377_amd import tuning
+    from paper_2502_06377_amd.flops import sweep_flops
     log("[batched] generating 256 matrices")
     mats = workloads.config4_batch()
     dev = []
@@ -107,7 +108,7 @@ def batched_bench(ib, torch, oracle):
     outs = batch.solve()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    flops = sum(oracle.flops_sweep(a.shape[0], oracle.partition(a.shape[0], 128, 16)) * o.sweeps
+    flops = sum(sweep_flops(a.shape[0], ib.ibmi_partition(a.shape[0], 128, 16)) * o.sweeps
                 for a, o in zip(mats, outs))
     batch.close()
     return {"matrices": len(mats), "s_per_batch": round(dt, 4), "plan_s": round(plan_s, 4),
@@ -147,6 +148,7 @@ def main():
     import torch
     import workloads
     import paper_2502_06377_amd as ib
+    from paper_2502_06377_amd.flops import plan_flops, sweep_flops
 
     if args.copy_calibration:
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
@@ -163,7 +165,6 @@ def main():
     A = torch.from_numpy(A_host).to(dev)
     H = torch.empty((p, p), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-    import oracle  # flop accounting of the algorithm (cost section), no compute
 
     def run_form(prec):
         log(f"[{prec}] plan")
@@ -199,8 +200,8 @@ def main():
     panel_cfg_default = "IBMI_CFG_PANEL" not in os.environ
     plan, ranges, plan_s, dt, kt, hist = run_form("fp64")
     K = len(ranges)
-    f_sweep = oracle.flops_sweep(p, ranges)
-    f_plan = oracle.flops_plan(p, ranges)
+    f_sweep = sweep_flops(p, ranges)
+    f_plan = plan_flops(p, ranges)
     ms_step = dt / args.steps * 1e3
     tflops = f_sweep * args.steps / dt / 1e12
     panel_ms, panel_n, panel_fl = kt["panel"]
@@ -290,7 +291,7 @@ def main():
     del H, A
     torch.cuda.empty_cache()
     if args.batched:
-        out["batched_form"] = batched_bench(ib, torch, oracle)
+        out["batched_form"] = batched_bench(ib, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(A_host, ranges, args.cpu_sets)

@@ -25,7 +25,7 @@ unpinned" except where a docstring says so.
 from .partition import partition, validate_blocks, complement
 from .ibmi import (
     IbmiError, plan, block_factors, initial_h, block_update, sweep, residual_fro, paper_error,
-    ibmi_solve, flops_plan, flops_sweep, correction_sweep, emulate_product, hr_error_bound,
+    ibmi_solve, correction_sweep, emulate_product, hr_error_bound,
 )
 from .cholinv import cholesky_inverse_loops
 from .exact import exact_ibmi, exact_residual_sq
@@ -33,7 +33,7 @@ from .exact import exact_ibmi, exact_residual_sq
 __all__ = [
     "partition", "validate_blocks", "complement", "IbmiError", "plan", "block_factors",
     "initial_h",
-    "block_update", "sweep", "residual_fro", "paper_error", "ibmi_solve", "flops_plan",
-    "flops_sweep", "correction_sweep", "emulate_product", "cholesky_inverse_loops",
+    "block_update", "sweep", "residual_fro", "paper_error", "ibmi_solve",
+    "correction_sweep", "emulate_product", "hr_error_bound", "cholesky_inverse_loops",
     "exact_ibmi", "exact_residual_sq",
 ]

@@ -368,29 +368,3 @@ def correction_sweep(a: np.ndarray, h: np.ndarray, blocks_plan: list, product: s
         h[np.ix_(i, ic)] = new_ic_i.T
         x = h[np.ix_(i, i)] + (r_cols[i, :] - delta.T @ a[np.ix_(ic, i)]) @ bp.ainv
         h[np.ix_(i, i)] = 0.5 * (x + x.T)
-
-
-# --------------------------------------------------------------------------------------
-# Algorithmic flop counts (what IBMI computes; used for TFLOP/s figures).
-# --------------------------------------------------------------------------------------
-
-def flops_plan(p: int, ranges) -> float:
-    """Cholesky b^3/3, triangular inverse and L^{-T} L^{-1} 2 b^3/3, W = A_I^{-1} A_{I,I^c} 2 b^2 c."""
-    tot = 0.0
-    for s, e in ranges:
-        b = e - s
-        c = p - b
-        tot += b ** 3 / 3.0 + 2.0 * b ** 3 / 3.0 + 2.0 * b * b * c
-    return tot
-
-
-def flops_sweep(p: int, ranges, with_residual: bool = True) -> float:
-    """Per set 2 b c^2 (W H_{I^c}) + 2 b^2 c (V W^T); plus 2 p^3 for ||I - A H||_F."""
-    tot = 0.0
-    for s, e in ranges:
-        b = e - s
-        c = p - b
-        tot += 2.0 * b * c * c + 2.0 * b * b * c
-    if with_residual:
-        tot += 2.0 * float(p) ** 3
-    return tot

@@ -122,3 +122,38 @@ def test_covariance_row_chunks_same_bits():
                                                          row_chunk=333):
         out[r0:r1] = rows
     assert np.array_equal(out, full)
+
+
+def test_oracle_only_where_allowed():
+    """The product package never imports the oracle, and bench.py touches it only in its
+    CPU-baseline leg (the GPU figures use the package's own flop counts)."""
+    import ast
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "paper_2502_06377_amd", "*.py")):
+        tree = ast.parse(open(path).read())
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                assert all(a.name.split(".")[0] != "oracle" for a in node.names), path
+            if isinstance(node, ast.ImportFrom):
+                assert (node.module or "").split(".")[0] != "oracle", path
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    allowed = set()
+    for node in ast.walk(tree):
+        if isinstance(node, ast.FunctionDef) and node.name == "cpu_baseline":
+            allowed |= {id(n) for n in ast.walk(node)}
+    for node in ast.walk(tree):
+        uses = (isinstance(node, ast.Name) and node.id == "oracle") or (
+            isinstance(node, ast.Import) and any(a.name == "oracle" for a in node.names))
+        if uses:
+            assert id(node) in allowed, f"bench.py line {node.lineno} uses the oracle"
+
+
+def test_sweep_flops_of_the_benchmark_workload():
+    """Per set 2bc^2 + 2b^2c plus 2p^3: 1.83e13 flops per sweep at p = 16384 (32 sets)."""
+    from paper_2502_06377_amd.flops import plan_flops, sweep_flops
+    ranges = oracle.partition(16384, 576, 64)
+    f = sweep_flops(16384, ranges)
+    assert abs(f / 1.83e13 - 1) < 0.005
+    b, c = 576, 16384 - 576
+    assert sweep_flops(16384, [(0, 576)], with_residual=False) == 2 * b * c * c + 2 * b * b * c
+    assert plan_flops(16384, [(0, 576)]) == b ** 3 + 2 * b * b * c
