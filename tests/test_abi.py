@@ -157,3 +157,60 @@ def test_sweep_flops_of_the_benchmark_workload():
     b, c = 576, 16384 - 576
     assert sweep_flops(16384, [(0, 576)], with_residual=False) == 2 * b * c * c + 2 * b * b * c
     assert plan_flops(16384, [(0, 576)]) == b ** 3 + 2 * b * b * c
+
+
+def test_entry_points_reject_bad_arguments_before_device_work(binding):
+    """Argument checks of the C ABI run on the host before any device call, so they are
+    exercised here with stand-in addresses that are never dereferenced: null pointers, bad
+    options, lda < p, a misaligned or too small workspace, A overlapping the workspace, and
+    calls on a null plan."""
+    m = binding
+    lib = m._lib
+    INV, OOM = m.IBMI_ERR_INVALID_ARG, m.IBMI_ERR_OUT_OF_MEMORY
+    p = 1000
+    o = m.make_options(p, 256, 32)
+    need = m.ibmi_workspace_bytes(o)
+    a_fake, w_fake = 1 << 40, 1 << 44  # far apart, 256-byte aligned, never touched
+    h = ctypes.c_void_p()
+
+    def plan(opts, a=a_fake, lda=p, w=w_fake, nbytes=need, out=True):
+        return lib.ibmi_plan(ctypes.byref(h) if out else None, ctypes.byref(opts) if opts else None,
+                             a, lda, w, nbytes, None)
+
+    assert plan(o, out=False) == INV
+    assert plan(None) == INV
+    assert plan(o, a=None) == INV
+    assert plan(o, w=None) == INV
+    assert plan(o, lda=p - 1) == INV
+    assert plan(o, w=w_fake + 8) == INV                     # workspace not 256-byte aligned
+    assert plan(o, nbytes=need - 1) == OOM
+    assert plan(o, w=a_fake + 8 * p) == INV                 # workspace inside A
+    for field, bad in (("tol", 0.0), ("max_sweeps", 0), ("precision", 4), ("init", 3),
+                       ("stop", 4), ("fixed_sweeps", -1)):
+        ob = m.make_options(p, 256, 32)
+        setattr(ob, field, bad)
+        assert plan(ob) == INV, field
+    ob = m.make_options(p, 256, 32, stop="rel_bound", lambda_min=0.0)
+    assert plan(ob) == INV
+    for pp, b, ov in ((0, 256, 32), (-5, 256, 32), (p, 0, 0), (p, 64, 64)):
+        assert plan(m.make_options(pp, b, ov), lda=max(pp, 1)) == INV, (pp, b, ov)
+    ob = m.make_options(p, bounds=[(0, 600), (700, 1000)])   # sets leave a gap
+    assert plan(ob) == INV
+    info = m.IbmiInfo()
+    r = ctypes.c_double()
+    assert lib.ibmi_solve(None, a_fake, p, ctypes.byref(info), None) == INV
+    assert lib.ibmi_sweep(None, a_fake, p, 0, ctypes.byref(r)) == INV
+    assert lib.ibmi_block_step(None, a_fake, p, 0) == INV
+    assert lib.ibmi_init_h(None, a_fake, p) == INV
+    assert lib.ibmi_residual(None, a_fake, p, ctypes.byref(r)) == INV
+    assert lib.ibmi_plan_destroy(None) == INV
+    bo = m.make_options(300, 128, 16)
+    ps = (ctypes.c_int64 * 1)(300)
+    ptrs = (ctypes.c_void_p * 1)(a_fake)
+    lds = (ctypes.c_int64 * 1)(300)
+    bh = ctypes.c_void_p()
+    assert lib.ibmi_batch_plan(ctypes.byref(bh), 0, ps, ptrs, lds, ctypes.byref(bo), w_fake,
+                               1 << 30, None) == INV
+    bo.precision = 1
+    assert lib.ibmi_batch_plan(ctypes.byref(bh), 1, ps, ptrs, lds, ctypes.byref(bo), w_fake,
+                               1 << 30, None) == INV
