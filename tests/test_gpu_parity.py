@@ -167,6 +167,46 @@ def test_not_spd_reports_block(ib):
     assert ei.value.status == ib.IBMI_ERR_NOT_SPD and ei.value.block == 1
 
 
+def test_nonfinite_inputs_are_reported(ib):
+    """NaN inside a diagonal block fails its Cholesky pivot (NOT_SPD with that block); NaN only
+    in an off-diagonal block surfaces as a NaN residual after the first sweep (NONFINITE): the
+    library does not scan A (the oracle rejects a non-finite A up front).  An Inf in the part
+    of a given initial H that the first set reads gives NONFINITE in both; one in rows the
+    first set overwrites is never read, and both solve normally."""
+    _say("nonfinite inputs p=300")
+    base = workloads.wishart_spd(300, np.random.default_rng(5))
+    ranges = [(0, 100), (100, 200), (200, 300)]
+    A = base.copy()
+    A[150, 151] = A[151, 150] = np.nan
+    with pytest.raises(ib.IbmiError) as ei:
+        ib.Plan(_dev(A), bounds=ranges)
+    assert ei.value.status == ib.IBMI_ERR_NOT_SPD and ei.value.block == 1
+    A = base.copy()
+    A[0, 299] = A[299, 0] = np.nan
+    plan = ib.Plan(_dev(A), bounds=ranges, max_sweeps=5)
+    with pytest.raises(ib.IbmiError) as ei:
+        plan.solve()
+    assert ei.value.status == ib.IBMI_ERR_NONFINITE
+    plan.close()
+    for (i, j), bad in (((150, 250), True), ((10, 250), False)):
+        h0 = np.eye(300)
+        h0[i, j] = h0[j, i] = np.inf
+        plan = ib.Plan(_dev(base), bounds=ranges, max_sweeps=5, tol=1e-300, init="given")
+        if bad:
+            with pytest.raises(oracle.IbmiError) as eo:
+                oracle.ibmi_solve(base, ranges, init="given", h0=h0, tol=1e-300, max_sweeps=5)
+            assert eo.value.code == "NONFINITE"
+            with pytest.raises(ib.IbmiError) as ei:
+                plan.solve(_dev(h0))
+            assert ei.value.status == ib.IBMI_ERR_NONFINITE
+        else:
+            ref = oracle.ibmi_solve(base, ranges, init="given", h0=h0, tol=1e-300, max_sweeps=5)
+            out = plan.solve(_dev(h0))
+            assert out.sweeps == ref.sweeps == 5
+            assert _rel(out.H.cpu().numpy(), ref.h) <= TOL
+        plan.close()
+
+
 def test_deterministic_and_resume(ib):
     _say("determinism and resume p=400")
     A = workloads.config2_matrix(p=400)
