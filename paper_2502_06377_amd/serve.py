@@ -95,7 +95,6 @@ class ServeStats:
     def summary(self, offered: int, budget: int) -> dict:
         lat = np.array([r.latency for r in self.results]) if self.results else np.array([0.0])
         done = len(self.results)
-        flops = 0.0
         return {"requests_offered": offered, "requests_done": done,
                 "wall_s": round(self.wall, 3), "solves_per_s": round(done / self.wall, 3),
                 "latency_p50_s": round(float(np.percentile(lat, 50)), 4),

@@ -214,3 +214,54 @@ def test_entry_points_reject_bad_arguments_before_device_work(binding):
     bo.precision = 1
     assert lib.ibmi_batch_plan(ctypes.byref(bh), 1, ps, ptrs, lds, ctypes.byref(bo), w_fake,
                                1 << 30, None) == INV
+
+
+def test_serving_footprint_and_summary(binding):
+    """Admission footprint = A + H (rows padded to 8 elements) + the plan's workspace; it grows
+    with p and the low-precision forms need more than FP64.  The summary's percentiles are
+    those of the recorded latencies."""
+    from paper_2502_06377_amd import serve
+    m = binding
+    for p in (512, 1000, 8192):
+        ld = (p + 7) // 8 * 8
+        ws = m.ibmi_workspace_bytes(m.make_options(p, 576, 64, tol=1e-10))
+        assert serve.footprint_bytes(p, "fp64", 576, 64, 1e-10) == 2 * p * ld * 8 + ws
+        assert serve.footprint_bytes(p, serve.LOW_FORM, 576, 64, 1e-6) > ws + 2 * p * ld * 8
+    sizes = [serve.footprint_bytes(p, "fp64", 576, 64, 1e-10) for p in (512, 1024, 4096, 8192)]
+    assert sizes == sorted(sizes)
+    st = serve.ServeStats(wall=2.0)
+    for i in range(100):
+        st.results.append(serve.Result(rid=i, p=512, tol=1e-10, form="fp64", arrival=0.0,
+                                       start=0.0, end=0.01 * (i + 1), sweeps=3, converged=True,
+                                       residual=0.0, footprint=0))
+    s = st.summary(120, 1 << 30)
+    assert s["requests_done"] == 100 and s["solves_per_s"] == 50.0
+    assert abs(s["latency_p50_s"] - 0.505) < 1e-9 and abs(s["latency_p99_s"] - 0.9901) < 1e-9
+    assert s["converged"] == 100 and s["capped_or_failed"] == 0
+
+
+def test_autotune_cache_round_trip(binding, tmp_path, monkeypatch):
+    """The batched form's tile cache: a miss runs the autotuner once and stores its choice; the
+    next lookup of the same key applies the stored choice without tuning."""
+    from paper_2502_06377_amd import tuning
+
+    class FakeBatch:
+        def __init__(self):
+            self.applied, self.tunes = None, 0
+
+        def autotune(self, reps):
+            self.tunes += 1
+            return (4, 1, 2), 12.5
+
+        def set_tuning(self, *cfg):
+            self.applied = cfg
+
+    monkeypatch.setattr(tuning, "batch_key", lambda b: "gfx950/batch/test")
+    path = str(tmp_path / "cache.json")
+    b1 = FakeBatch()
+    r1 = tuning.tuned(b1, path=path)
+    assert not r1["cached"] and b1.tunes == 1 and r1["cfg"] == (4, 1, 2)
+    b2 = FakeBatch()
+    r2 = tuning.tuned(b2, path=path)
+    assert r2["cached"] and b2.tunes == 0 and b2.applied == (4, 1, 2)
+    assert r2["ms_per_sweep"] == 12.5
