@@ -149,7 +149,10 @@ size_t ibmi_workspace_bytes(const ibmi_options* opts);
  *           aligned.  Borrowed like dA.
  *  stream   hipStream_t to enqueue on (NULL = default stream).
  * Synchronises the stream once to read the pivot status.  On NOT_SPD no plan is returned
- * and ibmi_plan_failed_block() reports the set.  *out is set only on IBMI_OK. */
+ * and ibmi_plan_failed_block() reports the set.  *out is set only on IBMI_OK.
+ * A is not scanned for NaN/Inf: one inside a diagonal block fails that set's pivot test
+ * (NOT_SPD); one elsewhere reaches W and is reported by the first sweep (NONFINITE).
+ * Every argument check (INVALID_ARG, OUT_OF_MEMORY) runs on the host before device work. */
 ibmi_status ibmi_plan(ibmi_plan_t* out, const ibmi_options* opts, const double* dA, int64_t lda,
                       void* dWork, size_t work_bytes, void* stream);
 
@@ -175,9 +178,9 @@ typedef int32_t (*ibmi_progress_fn)(int32_t sweep, double residual, double stop_
 ibmi_status ibmi_set_progress(ibmi_plan_t plan, ibmi_progress_fn fn, void* user);
 
 /* One sweep (sets k = 1..K in order) in the plan's precision form, then ||I - A H||_F written
- * to *residual (host, nullable); synchronises once.  The FP32-update form carries the
- * residual matrix of the previous sweep in the workspace: pass restart = 1 on the first call
- * for an H, or whenever H was changed by anything but ibmi_sweep on this plan.
+ * to *residual (host, nullable); synchronises once.  The low-precision update forms carry
+ * the residual matrix of the previous sweep in the workspace: pass restart = 1 on the first
+ * call for an H, or whenever H was changed by anything but ibmi_sweep on this plan.
  * NONFINITE if the residual is NaN/Inf. */
 ibmi_status ibmi_sweep(ibmi_plan_t plan, double* dH, int64_t ldh, int32_t restart,
                        double* residual);
