@@ -1,4 +1,4 @@
-// FP32 GEMM launch of the FP32-update form.
+// FP32 GEMM launch of the FP32 update form.
 #include "gemm.h"
 
 namespace ibmi {

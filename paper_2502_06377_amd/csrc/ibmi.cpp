@@ -534,10 +534,10 @@ static ibmi_status block_step(ibmi_plan_t P, double* dH, int64_t ldh, int k) {
 static ibmi_status residual_sq(ibmi_plan_t P, const double* dH, int64_t ldh, bool want_h,
                                double* res_sq, double* h_sq, double* store);
 
-// One set of the FP32-update (correction) form.  On entry rt holds R_s^T = I - A H_s for the
-// H at the start of the sweep and dmat holds D = H - H_s in FP32; u is the end of the union of
-// the sets already updated in this sweep (D vanishes outside rows/columns [0,u)).
-//   RkT   = R_s^T[I,:] - A[:,I]^T D       (FP32 matrix cores, FP32 accumulation)
+// One set of a low-precision update (correction) form.  On entry rt holds R_s^T = I - A H_s
+// for the H at the start of the sweep and dmat holds D = H - H_s in FP32; u is the end of the
+// union of the sets already updated in this sweep (D vanishes outside rows/columns [0,u)).
+//   RkT   = R_s^T[I,:] - A[:,I]^T D       (FP32 or split-bfloat16 matrix cores, FP32 sums)
 //   Delta = R[I^c,I] A_I^{-1}             H[I^c,I] += Delta, mirrored; D likewise
 //   T     = R[I,I] - Delta^T A[I^c,I]     (split-K, fixed-order sum)
 //   H[I,I] += sym(T A_I^{-1});  D[I,I] likewise
@@ -586,7 +586,7 @@ static ibmi_status block_step_mixed(ibmi_plan_t P, double* dH, int64_t ldh, int 
 }
 
 // One full sweep of the plan's form followed by the residual; restart recomputes the
-// starting residual of the FP32-update form from H.
+// starting residual of the low-precision update forms from H.
 static ibmi_status sweep_once(ibmi_plan_t P, double* dH, int64_t ldh, bool restart, bool want_h,
                               double* res_sq, double* h_sq) {
   const int K = (int)P->s.size();

@@ -41,7 +41,7 @@ enum {
   EPI_RESID = 3,        // red[slot] = sum over the tile of (delta_mn - C)^2
   EPI_RESID_STORE = 4,  // out[m][n] = delta_mn - C and red[slot] = sum of its squares
   EPI_SUBFROM = 5,      // out[m][n] = src[(s+m)][n] - C
-  EPI_CORR = 6,         // correction of H[I^c,I] and D (FP32-update form)
+  EPI_CORR = 6,         // correction of H[I^c,I] and D (low-precision update forms)
   EPI_SUMSQ = 7         // red[slot] = sum over the tile of C^2
 };
 

@@ -1,6 +1,6 @@
 // gfx950 (CDNA4) kernels of the IBMI library other than the GEMMs: block factors (Cholesky,
-// L^{-1}; once per plan), diagonal finalisation, initialisation, reductions, the FP32-update
-// helpers and the batched-form bookkeeping.  The GEMM templates live in gemm.h.
+// L^{-1}; once per plan), diagonal finalisation, initialisation, reductions, the helpers of
+// the low-precision update forms and the batched-form bookkeeping.  The GEMM templates live in gemm.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -298,7 +298,7 @@ hipError_t reduce_sum(const double* red, int64_t n, double* out, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------------------
-// Mixed (FP32-update) form helpers.
+// Helpers of the low-precision update (correction) forms.
 // ---------------------------------------------------------------------------------------
 __global__ void to_f32_kernel(const double* a, int64_t lda, float* out, int64_t ldo, int64_t p) {
   const int64_t n = p * ldo;
