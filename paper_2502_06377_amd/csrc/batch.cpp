@@ -575,8 +575,11 @@ ibmi_status ibmi_batch_autotune(ibmi_batch_t B, double* const* dH, const int64_t
                                 {GEMM_64x128_K16, GEMM_64x64_K16, GEMM_64x128_K16},
                                 {GEMM_64x64_W2, GEMM_64x64_W2, GEMM_64x64_K16}};
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  BHIP(hipEventCreate(&e0));
-  BHIP(hipEventCreate(&e1));
+  if (hipEventCreate(&e0) != hipSuccess) return IBMI_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return IBMI_ERR_HIP;
+  }
   double best = 1e300;
   int bi = 0;
   ibmi_status rc = IBMI_OK;
