@@ -240,7 +240,7 @@ def test_serving_footprint_and_summary(binding):
     assert s["converged"] == 100 and s["capped_or_failed"] == 0
 
 
-def test_autotune_cache_round_trip(binding, tmp_path, monkeypatch):
+def test_autotune_cache_round_trip(binding, monkeypatch):
     """The batched form's tile cache: a miss runs the autotuner once and stores its choice; the
     next lookup of the same key applies the stored choice without tuning."""
     from paper_2502_06377_amd import tuning
@@ -257,7 +257,10 @@ def test_autotune_cache_round_trip(binding, tmp_path, monkeypatch):
             self.applied = cfg
 
     monkeypatch.setattr(tuning, "batch_key", lambda b: "gfx950/batch/test")
-    path = str(tmp_path / "cache.json")
+    os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
+    path = os.path.join(ROOT, "_build", "test_tune_cache.json")
+    if os.path.exists(path):
+        os.remove(path)
     b1 = FakeBatch()
     r1 = tuning.tuned(b1, path=path)
     assert not r1["cached"] and b1.tunes == 1 and r1["cfg"] == (4, 1, 2)
