@@ -246,7 +246,8 @@ ibmi_status ibmi_batch_solve(ibmi_batch_t batch, double* const* dH, const int64_
                              ibmi_info* infos);
 
 /* Tile configurations (0 <= cfg < 11; see the GEMM configuration table in the sources) of
- * the grouped panel, diagonal and residual launches. */
+ * the grouped panel, diagonal and residual launches; INVALID_ARG outside that range.  A new
+ * choice takes effect at the next ibmi_batch_solve (the graph is captured again). */
 ibmi_status ibmi_batch_set_tuning(ibmi_batch_t batch, int32_t panel, int32_t diag,
                                   int32_t resid);
 ibmi_status ibmi_batch_get_tuning(ibmi_batch_t batch, int32_t* cfg3);
@@ -257,6 +258,10 @@ ibmi_status ibmi_batch_get_tuning(ibmi_batch_t batch, int32_t* cfg3);
 ibmi_status ibmi_batch_autotune(ibmi_batch_t batch, double* const* dH, const int64_t* ldh,
                                 int32_t reps, int32_t* cfg3, double* ms_per_sweep);
 
+/* Release the batch object with its task tables and captured graph (ibmi_batch_solve and
+ * ibmi_batch_autotune synchronise before they return, so no replay is in flight between
+ * calls).  A, H and the workspace are the caller's and stay untouched.  INVALID_ARG for a
+ * NULL batch. */
 ibmi_status ibmi_batch_destroy(ibmi_batch_t batch);
 
 #ifdef __cplusplus
