@@ -242,6 +242,27 @@ def test_block_diagonal_matrix_converges_in_one_sweep():
     assert _rel(res.h, np.linalg.inv(A)) < 1e-13
 
 
+def test_initial_guesses():
+    """Identity is I; the block-diagonal guess holds each disjoint set's inverse (LAPACK's
+    LU-based inverse, not the oracle's Cholesky route) and zeros elsewhere, and needs disjoint
+    sets; a given H0 is copied, not aliased."""
+    A = _spd(13, 4)
+    sets = [(0, 4), (4, 9), (9, 13)]
+    P = oracle.plan(A, sets)
+    assert np.array_equal(oracle.initial_h(A, P, "identity"), np.eye(13))
+    H = oracle.initial_h(A, P, "blockdiag_inv")
+    want = np.zeros((13, 13))
+    for s, e in sets:
+        want[s:e, s:e] = np.linalg.inv(A[s:e, s:e])
+    assert np.abs(H - want).max() < 1e-12 * np.abs(want).max()
+    assert np.array_equal(H, H.T)
+    h0 = _spd(13, 5)
+    G = oracle.initial_h(A, P, "given", h0)
+    assert np.array_equal(G, h0) and G is not h0
+    with pytest.raises(oracle.IbmiError):
+        oracle.initial_h(A, oracle.plan(A, [(0, 6), (4, 13)]), "blockdiag_inv")
+
+
 def test_fixed_point():
     A = _spd(16, 9)
     sigma = np.linalg.inv(A)
