@@ -167,6 +167,7 @@ def test_not_spd_reports_block(ib):
     assert ei.value.status == ib.IBMI_ERR_NOT_SPD and ei.value.block == 1
 
 
+@pytest.mark.filterwarnings("ignore:invalid value encountered:RuntimeWarning")
 def test_nonfinite_inputs_are_reported(ib):
     """NaN inside a diagonal block fails its Cholesky pivot (NOT_SPD with that block); NaN only
     in an off-diagonal block surfaces as a NaN residual after the first sweep (NONFINITE): the

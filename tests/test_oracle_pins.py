@@ -350,6 +350,7 @@ def test_partition_merges_short_last_core():
 
 # ---------------------------------------------------------------- errors
 
+@pytest.mark.filterwarnings("ignore:invalid value encountered:RuntimeWarning")
 def test_error_paths():
     A = _spd(10, 1)
     bad = A.copy()
