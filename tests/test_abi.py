@@ -268,3 +268,17 @@ def test_autotune_cache_round_trip(binding, monkeypatch):
     r2 = tuning.tuned(b2, path=path)
     assert r2["cached"] and b2.tunes == 0 and b2.applied == (4, 1, 2)
     assert r2["ms_per_sweep"] == 12.5
+
+
+def test_bench_traffic_only_for_the_profiled_kernel():
+    """The bench's roofline `traffic` comes from the committed PMC summary and only while that
+    summary names the panel kernel instantiation the bench runs; any other name gives None."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t = bench.measured_traffic(bench.PANEL_KERNEL)
+    assert t is not None and 1e9 < t < 1e11
+    assert bench.measured_traffic(bench.PANEL_KERNEL.replace("96, 64", "64, 64")) is None
+    profile = open(os.path.join(ROOT, "profiles", "ibmi_sweep_p16384_kernel_stats.md")).read()
+    assert bench.PANEL_KERNEL in profile
